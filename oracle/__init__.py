@@ -1,0 +1,258 @@
+"""ORACLE -- test infrastructure only.
+
+Python access to the plain FP64 CPU implementation in ``fade_oracle.c`` of the
+lattice Boltzmann scheme for the space-fractional advection-diffusion equation
+(Cartalade, Younsi, Neel, arXiv:1706.09161).  Only ``tests/``, the smoke check
+and the benchmark's CPU-baseline leg import this package; the GPU library never
+does.  It shares no code with the GPU path: both sides read their inputs from
+``synth`` (seeded generators that hold none of the method's arithmetic).
+
+``oracle.adjoint`` adds the hand-written FP64 adjoint of the same step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfade_oracle.so")
+_SOURCES = ["fade_oracle.c", "fade_oracle_adjoint.c"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas",
+               "-o", tmp, *srcs, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Problem(ctypes.Structure):
+    """Mirror of ``fo_problem`` in fade_oracle.c."""
+
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("collision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("alpha", ctypes.c_double * 3),
+        ("p", ctypes.c_double * 3),
+        ("g", ctypes.c_double * 3),
+        ("D", ctypes.c_double * 9),
+        ("u", ctypes.c_double * 3),
+        ("tau_free", ctypes.c_double * 4),
+        ("tau0", ctypes.c_double),
+        ("c_wall", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER(Problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        sig = {
+            "fo_lattice": (ctypes.c_int, [ctypes.c_int32, i32p, i32p, dp, dp]),
+            "fo_cplus": (ctypes.c_double, [ctypes.c_int64, ctypes.c_int64, ctypes.c_double]),
+            "fo_cminus": (ctypes.c_double, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_double]),
+            "fo_phi": (ctypes.c_int, [P, dp, dp]),
+            "fo_phi_at": (ctypes.c_int, [P, dp, ip, ctypes.c_int64, dp]),
+            "fo_collision_matrices": (ctypes.c_int, [P, dp, dp, dp, dp]),
+            "fo_equilibrium": (ctypes.c_int, [P, ctypes.c_double, dp, dp]),
+            "fo_collide_node": (ctypes.c_int, [P, dp, ctypes.c_double, dp, ctypes.c_double, dp]),
+            "fo_moment": (ctypes.c_int, [P, dp, dp]),
+            "fo_init": (ctypes.c_int, [P, dp, dp]),
+            "fo_step": (ctypes.c_int, [P, dp, dp, ctypes.c_int64]),
+            "fo_step_sampled": (ctypes.c_int, [P, dp, dp, ip, ctypes.c_int64, dp]),
+        }
+        if hasattr(L, "fo_adjoint"):
+            sig["fo_adjoint"] = (ctypes.c_int, [P, dp, dp, ctypes.c_int64, dp, dp, dp, dp, dp, dp])
+            sig["fo_step_linear"] = (ctypes.c_int, [P, dp, dp, ctypes.c_int64])
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def make_problem(cfg: dict) -> Problem:
+    """Build the C struct from a plain configuration dict (see ``synth``)."""
+    P = Problem()
+    d = int(cfg["dim"])
+    P.dim = d
+    for mu in range(3):
+        P.n[mu] = int(cfg["n"][mu]) if mu < d else 1
+    P.collision = {"BGK": 0, "MRT": 1}[cfg.get("collision", "MRT")]
+    P.dx = float(cfg.get("dx", 1.0))
+    P.dt = float(cfg.get("dt", 1.0))
+    for mu in range(d):
+        P.alpha[mu] = float(cfg["alpha"][mu])
+        P.p[mu] = float(cfg["p"][mu])
+        P.g[mu] = float(cfg.get("g", [1.0] * d)[mu])
+        P.u[mu] = float(cfg.get("u", [0.0] * d)[mu])
+    D = np.asarray(cfg["D"], dtype=np.float64).reshape(d, d)
+    for a in range(d):
+        for b in range(d):
+            P.D[a * d + b] = float(D[a, b])
+    tf = cfg.get("tau_free", [1.0] * 4)
+    for k in range(4):
+        P.tau_free[k] = float(tf[k]) if k < len(tf) else 1.0
+    P.tau0 = float(cfg.get("tau0", 1.0))
+    P.c_wall = float(cfg.get("c_wall", 0.0))
+    return P
+
+
+def shape_of(cfg: dict):
+    """Array shape (slowest first) of a node field: (ny, nx) or (nz, ny, nx)."""
+    return tuple(int(v) for v in reversed(cfg["n"][: cfg["dim"]]))
+
+
+def Q_of(cfg: dict) -> int:
+    return 2 * int(cfg["dim"]) + 1
+
+
+def lattice(dim: int):
+    Q = ctypes.c_int32()
+    e = np.zeros(21, dtype=np.int32)
+    w = np.zeros(7)
+    e2 = ctypes.c_double()
+    _check(lib().fo_lattice(dim, ctypes.byref(Q), e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
+                            ctypes.byref(e2)), "lattice")
+    q = Q.value
+    return e.reshape(7, 3)[:q, :dim].copy(), w[:q].copy(), e2.value
+
+
+def cplus(l: int, n: int, gamma: float) -> float:
+    return lib().fo_cplus(l, n, gamma)
+
+
+def cminus(l: int, n: int, N: int, gamma: float) -> float:
+    return lib().fo_cminus(l, n, N, gamma)
+
+
+def phi(cfg: dict, C: np.ndarray) -> np.ndarray:
+    """Fractional terms Phi_mu for every node: array (d, *shape)."""
+    P = make_problem(cfg)
+    C = np.ascontiguousarray(C, dtype=np.float64).reshape(shape_of(cfg))
+    out = np.zeros((cfg["dim"],) + C.shape)
+    _check(lib().fo_phi(ctypes.byref(P), _dp(C), _dp(out)), "phi")
+    return out
+
+
+def phi_at(cfg: dict, C: np.ndarray, nodes: np.ndarray) -> np.ndarray:
+    P = make_problem(cfg)
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros((cfg["dim"], nodes.size))
+    _check(lib().fo_phi_at(ctypes.byref(P), _dp(C), _ip(nodes), nodes.size, _dp(out)), "phi_at")
+    return out
+
+
+def collision_matrices(cfg: dict):
+    P = make_problem(cfg)
+    Q = Q_of(cfg)
+    M = np.zeros((Q, Q))
+    Mi = np.zeros((Q, Q))
+    Lam = np.zeros((Q, Q))
+    lam = ctypes.c_double()
+    _check(lib().fo_collision_matrices(ctypes.byref(P), _dp(M), _dp(Mi), _dp(Lam), ctypes.byref(lam)),
+           "collision_matrices")
+    return M, Mi, Lam, lam.value
+
+
+def equilibrium(cfg: dict, C: float, phi_node) -> np.ndarray:
+    P = make_problem(cfg)
+    ph = np.ascontiguousarray(phi_node, dtype=np.float64)
+    out = np.zeros(Q_of(cfg))
+    _check(lib().fo_equilibrium(ctypes.byref(P), float(C), _dp(ph), _dp(out)), "equilibrium")
+    return out
+
+
+def collide_node(cfg: dict, f_node, C: float, phi_node, S: float = 0.0) -> np.ndarray:
+    P = make_problem(cfg)
+    f = np.ascontiguousarray(f_node, dtype=np.float64)
+    ph = np.ascontiguousarray(phi_node, dtype=np.float64)
+    out = np.zeros(Q_of(cfg))
+    _check(lib().fo_collide_node(ctypes.byref(P), _dp(f), float(C), _dp(ph), float(S), _dp(out)), "collide")
+    return out
+
+
+def moment(cfg: dict, f: np.ndarray) -> np.ndarray:
+    P = make_problem(cfg)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(shape_of(cfg))
+    _check(lib().fo_moment(ctypes.byref(P), _dp(f), _dp(out)), "moment")
+    return out
+
+
+def init(cfg: dict, C0: np.ndarray) -> np.ndarray:
+    """Initial populations f = f^eq(C0 with walls := c_wall): array (Q, *shape)."""
+    P = make_problem(cfg)
+    C0 = np.ascontiguousarray(C0, dtype=np.float64).reshape(shape_of(cfg))
+    f = np.zeros((Q_of(cfg),) + C0.shape)
+    _check(lib().fo_init(ctypes.byref(P), _dp(C0), _dp(f)), "init")
+    return f
+
+
+def step(cfg: dict, f: np.ndarray, nsteps: int, S: np.ndarray | None = None) -> np.ndarray:
+    """Advance populations by nsteps time steps; returns a new array."""
+    P = make_problem(cfg)
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    Sp = None
+    if S is not None:
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(shape_of(cfg))
+        Sp = _dp(S)
+    _check(lib().fo_step(ctypes.byref(P), _dp(f), Sp, int(nsteps)), "step")
+    return f
+
+
+def step_sampled(cfg: dict, f: np.ndarray, nodes: np.ndarray, S: np.ndarray | None = None) -> np.ndarray:
+    """One step from full state f, evaluated at the given flat node indices: (Q, count)."""
+    P = make_problem(cfg)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    Sp = None
+    if S is not None:
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        Sp = _dp(S)
+    out = np.zeros((Q_of(cfg), nodes.size))
+    _check(lib().fo_step_sampled(ctypes.byref(P), _dp(f), Sp, _ip(nodes), nodes.size, _dp(out)), "step_sampled")
+    return out
+
+
+def run(cfg: dict, C0: np.ndarray, nsteps: int, S: np.ndarray | None = None) -> np.ndarray:
+    """C after nsteps from the initial concentration C0."""
+    f = init(cfg, C0)
+    f = step(cfg, f, nsteps, S)
+    return moment(cfg, f)

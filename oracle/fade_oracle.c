@@ -1,0 +1,736 @@
+/*
+ * fade_oracle.c -- ORACLE.  Test infrastructure only.
+ *
+ * A plain, scalar, double-precision CPU implementation of the lattice
+ * Boltzmann (LB) scheme for the space-fractional advection-diffusion
+ * equation (FADE) of Cartalade, Younsi and Neel, "Multiple-Relaxation-Time
+ * Lattice Boltzmann scheme for Fractional Advection-Diffusion Equation"
+ * (arXiv:1706.09161).  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library; the GPU library neither
+ * links nor calls it, and the two share no code, header or table.
+ *
+ * The method is an explicit iteration, so this file executes the steps of
+ * the paper's Algorithm 1 in the paper's order and notation: the discrete
+ * fractional integrals are direct sums with the trapezoidal product-rule
+ * coefficients evaluated exactly as printed (Sec. 2.4), the collision is the
+ * literal matrix product M^-1 Lambda M (f - f^eq) (Sec. 2.3) with M^-1 and
+ * Lambda obtained by Gauss-Jordan inversion, and streaming and the Dirichlet
+ * rule are applied node by node (Sec. 2.2, Sec. 2.5).  No blocking, fusion
+ * or reordering is done beyond what those definitions state.
+ *
+ * Readings taken where the paper is silent or ambiguous (each one is also
+ * repeated at its point of use):
+ *   - grid size n[mu] counts nodes per axis INCLUDING both wall nodes, so the
+ *     paper's N_mu = n[mu] - 1 and node indices run 0..N_mu (Sec. 2.4);
+ *   - c+_{00} and c-_{NN}: the "l = n" branch applies, value 1 (Sec. 2.4);
+ *   - a wall node with several unknown populations (2D corners, 3D edges and
+ *     corners) shares the Dirichlet deficit equally among them (Sec. 2.5);
+ *   - initial populations are the equilibrium of the initial concentration,
+ *     after the wall nodes have been overwritten with the wall value;
+ *   - the D2Q5 relaxation matrix is blockdiag(tau0, lambda-bar (2x2),
+ *     tau_free[0], tau_free[1]) for moment rows 3 and 4 of M (Sec. 2.3);
+ *   - the "relaxation rates" lambda of the paper are relaxation TIMES: the
+ *     collision uses 1/lambda (Sec. 2.2) and D = e^2 (lambda - 1/2) dx^2/dt;
+ *   - the source enters after collision with weight w_i S dt (Sec. 2.2).
+ *
+ * Layout: node index x + nx*(y + ny*z) (x fastest); populations
+ * f[i*nodes + node]; fractional terms Phi[mu*nodes + node].
+ * Threads (OpenMP) only split independent nodes or lines: every value is
+ * summed by one thread in a fixed order, so results do not depend on the
+ * thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define FO_OK 0
+#define FO_EINVAL (-1)
+#define FO_ENOMEM (-2)
+
+typedef struct {
+    int32_t dim;        /* 2 (D2Q5) or 3 (D3Q7) */
+    int32_t n[3];       /* nodes per axis, both wall nodes included */
+    int32_t collision;  /* 0 = BGK, 1 = MRT */
+    int32_t reserved;
+    double dx, dt;
+    double alpha[3];    /* in (1, 2] */
+    double p[3];        /* in [0, 1] */
+    double g[3];        /* > 0 */
+    double D[9];        /* d x d, row-major */
+    double u[3];
+    double tau_free[4]; /* relaxation times of the moments beyond the fluxes (MRT) */
+    double tau0;        /* relaxation time of the mass moment (no effect) */
+    double c_wall;      /* Dirichlet value on every wall node */
+} fo_problem;
+
+/* ------------------------------------------------------------------------ */
+/* Lattices D2Q5 and D3Q7 (Sec. 2.1 and the caption of the lattice figure):
+ * e_0 = 0, e_{2mu-1} = +b_mu, e_{2mu} = -b_mu; D2Q5: w0 = 1/3, w_i = 1/6,
+ * e^2 = 1/3; D3Q7: w0 = 1/4, w_i = 1/8, e^2 = 1/4. */
+typedef struct {
+    int Q;
+    int e[7][3];
+    double w[7];
+    double e2;
+} fo_lattice_t;
+
+static int lattice_of(int dim, fo_lattice_t* L)
+{
+    if (dim != 2 && dim != 3) return FO_EINVAL;
+    memset(L, 0, sizeof(*L));
+    L->Q = 2 * dim + 1;
+    for (int mu = 0; mu < dim; ++mu) {
+        L->e[2 * mu + 1][mu] = 1;
+        L->e[2 * mu + 2][mu] = -1;
+    }
+    if (dim == 2) {
+        L->w[0] = 1.0 / 3.0;
+        for (int i = 1; i < 5; ++i) L->w[i] = 1.0 / 6.0;
+        L->e2 = 1.0 / 3.0;
+    } else {
+        L->w[0] = 1.0 / 4.0;
+        for (int i = 1; i < 7; ++i) L->w[i] = 1.0 / 8.0;
+        L->e2 = 1.0 / 4.0;
+    }
+    return FO_OK;
+}
+
+int fo_lattice(int32_t dim, int32_t* Q, int32_t* e /* 7x3 */, double* w /* 7 */, double* e2)
+{
+    fo_lattice_t L;
+    if (lattice_of(dim, &L) != FO_OK) return FO_EINVAL;
+    *Q = L.Q;
+    for (int i = 0; i < 7; ++i)
+        for (int c = 0; c < 3; ++c) e[3 * i + c] = L.e[i][c];
+    for (int i = 0; i < 7; ++i) w[i] = L.w[i];
+    *e2 = L.e2;
+    return FO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trapezoidal product-rule coefficients for the left fractional integral,
+ * equation (c+) of Sec. 2.4 (after Diethelm et al.).  Defined for 0 <= l <= n;
+ * zero outside the summation range.  Reading: at l = n = 0 both the l = 0 and
+ * the l = n branches apply; the l = n branch is taken (value 1), which keeps
+ * the gamma = 0 operator equal to the identity. */
+double fo_cplus(int64_t l, int64_t n, double gamma)
+{
+    if (l < 0 || l > n) return 0.0;
+    if (l == n) return 1.0;
+    const double gp1 = gamma + 1.0;
+    if (l == 0)
+        return (1.0 + gamma) * pow((double)n, gamma) - pow((double)n, gp1) + pow((double)(n - 1), gp1);
+    return pow((double)(n - l + 1), gp1) - 2.0 * pow((double)(n - l), gp1) + pow((double)(n - l - 1), gp1);
+}
+
+/* Coefficients for the right fractional integral, equation (c-) of Sec. 2.4.
+ * Defined for n <= l <= N; zero outside.  Same reading at l = n = N. */
+double fo_cminus(int64_t l, int64_t n, int64_t N, double gamma)
+{
+    if (l < n || l > N) return 0.0;
+    if (l == n) return 1.0;
+    const double gp1 = gamma + 1.0;
+    if (l == N)
+        return (1.0 + gamma) * pow((double)(N - n), gamma) - pow((double)(N - n), gp1) + pow((double)(N - n - 1), gp1);
+    return pow((double)(l - n + 1), gp1) - 2.0 * pow((double)(l - n), gp1) + pow((double)(l - n - 1), gp1);
+}
+
+/* ------------------------------------------------------------------------ */
+static int64_t nodes_of(const fo_problem* P)
+{
+    int64_t m = 1;
+    for (int mu = 0; mu < P->dim; ++mu) m *= P->n[mu];
+    return m;
+}
+
+static int64_t stride_of(const fo_problem* P, int mu)
+{
+    int64_t s = 1;
+    for (int nu = 0; nu < mu; ++nu) s *= P->n[nu];
+    return s;
+}
+
+static void coords_of(const fo_problem* P, int64_t node, int64_t x[3])
+{
+    x[0] = x[1] = x[2] = 0;
+    for (int mu = 0; mu < P->dim; ++mu) {
+        x[mu] = node % P->n[mu];
+        node /= P->n[mu];
+    }
+}
+
+static int validate(const fo_problem* P)
+{
+    if (P->dim != 2 && P->dim != 3) return FO_EINVAL;
+    if (!(P->dx > 0.0) || !(P->dt > 0.0)) return FO_EINVAL;
+    for (int mu = 0; mu < P->dim; ++mu) {
+        if (P->n[mu] < 3) return FO_EINVAL;
+        if (!(P->alpha[mu] > 1.0 && P->alpha[mu] <= 2.0)) return FO_EINVAL;
+        if (!(P->p[mu] >= 0.0 && P->p[mu] <= 1.0)) return FO_EINVAL;
+        if (!(P->g[mu] > 0.0)) return FO_EINVAL;
+    }
+    if (P->collision != 0 && P->collision != 1) return FO_EINVAL;
+    return FO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The fractional term of Algorithm 1 (time loop, first stage), for every node
+ * and axis, by the discrete integrals of equation (XXminus_discret), Sec. 2.4:
+ *   Phi_mu(x) = p_mu I+^{gamma_mu}(g_mu C)(x) + (1 - p_mu) I-^{gamma_mu}(g_mu C)(x),
+ *   I+ = dx^gamma / Gamma(2+gamma) * sum_{l=0}^{n} c+_{ln} g C(y_l),
+ *   I- = dx^gamma / Gamma(2+gamma) * sum_{l=n}^{N} c-_{ln} g C(y_l),
+ * with gamma_mu = 2 - alpha_mu, y_l the node of the same line with index l
+ * along mu, and the sums running over every node of the line, wall nodes
+ * included.  The coefficients c+-_{ln} are tabulated once per axis from the
+ * printed formulas; each sum is then taken term by term in increasing l. */
+typedef struct {
+    int64_t N;
+    double* cp; /* (N+1)^2, cp[n*(N+1) + l] = c+_{ln} */
+    double* cm; /* (N+1)^2, cm[n*(N+1) + l] = c-_{ln} */
+} coeff_table;
+
+static int make_table(int64_t N, double gamma, coeff_table* T)
+{
+    const int64_t m = N + 1;
+    T->N = N;
+    T->cp = (double*)malloc(sizeof(double) * m * m);
+    T->cm = (double*)malloc(sizeof(double) * m * m);
+    if (!T->cp || !T->cm) {
+        free(T->cp);
+        free(T->cm);
+        return FO_ENOMEM;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < m; ++n)
+        for (int64_t l = 0; l < m; ++l) {
+            T->cp[n * m + l] = fo_cplus(l, n, gamma);
+            T->cm[n * m + l] = fo_cminus(l, n, N, gamma);
+        }
+    return FO_OK;
+}
+
+static void free_table(coeff_table* T)
+{
+    free(T->cp);
+    free(T->cm);
+    T->cp = T->cm = NULL;
+}
+
+/* Phi_mu at index n of one line whose concentrations are line[0..N]. */
+static double phi_on_line(const coeff_table* T, const double* line, int64_t n,
+                          double p, double g, double pref)
+{
+    const int64_t m = T->N + 1;
+    double splus = 0.0, sminus = 0.0;
+    for (int64_t l = 0; l <= n; ++l) splus += T->cp[n * m + l] * (g * line[l]);
+    for (int64_t l = n; l <= T->N; ++l) sminus += T->cm[n * m + l] * (g * line[l]);
+    return p * (pref * splus) + (1.0 - p) * (pref * sminus);
+}
+
+int fo_phi(const fo_problem* P, const double* C, double* Phi)
+{
+    int rc = validate(P);
+    if (rc) return rc;
+    const int64_t nodes = nodes_of(P);
+    for (int mu = 0; mu < P->dim; ++mu) {
+        const int64_t len = P->n[mu], N = len - 1, s = stride_of(P, mu);
+        const int64_t lines = nodes / len;
+        const double gamma = 2.0 - P->alpha[mu];
+        const double pref = pow(P->dx, gamma) / tgamma(2.0 + gamma);
+        coeff_table T;
+        if (make_table(N, gamma, &T)) return FO_ENOMEM;
+        double* out = Phi + (int64_t)mu * nodes;
+        int failed = 0;
+#pragma omp parallel
+        {
+            double* line = (double*)malloc(sizeof(double) * len);
+            if (!line) {
+#pragma omp atomic write
+                failed = 1;
+            } else {
+#pragma omp for schedule(static)
+                for (int64_t q = 0; q < lines; ++q) {
+                    /* first node of line q: split q into the index below mu
+                     * (stride < s) and the index above mu */
+                    const int64_t base = (q % s) + (q / s) * s * len;
+                    for (int64_t l = 0; l < len; ++l) line[l] = C[base + l * s];
+                    for (int64_t n = 0; n < len; ++n)
+                        out[base + n * s] = phi_on_line(&T, line, n, P->p[mu], P->g[mu], pref);
+                }
+                free(line);
+            }
+        }
+        free_table(&T);
+        if (failed) return FO_ENOMEM;
+    }
+    return FO_OK;
+}
+
+/* Same sums, evaluated only at the listed nodes: Phi[mu*count + k]. */
+int fo_phi_at(const fo_problem* P, const double* C, const int64_t* which, int64_t count, double* Phi)
+{
+    int rc = validate(P);
+    if (rc) return rc;
+    const int64_t nodes = nodes_of(P);
+    for (int64_t k = 0; k < count; ++k)
+        if (which[k] < 0 || which[k] >= nodes) return FO_EINVAL;
+    for (int mu = 0; mu < P->dim; ++mu) {
+        const int64_t len = P->n[mu], N = len - 1, s = stride_of(P, mu);
+        const double gamma = 2.0 - P->alpha[mu];
+        const double pref = pow(P->dx, gamma) / tgamma(2.0 + gamma);
+        const double p = P->p[mu], g = P->g[mu];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t k = 0; k < count; ++k) {
+            const int64_t node = which[k];
+            const int64_t n = (node / s) % len;
+            const int64_t base = node - n * s;
+            double splus = 0.0, sminus = 0.0;
+            for (int64_t l = 0; l <= n; ++l) splus += fo_cplus(l, n, gamma) * (g * C[base + l * s]);
+            for (int64_t l = n; l <= N; ++l) sminus += fo_cminus(l, n, N, gamma) * (g * C[base + l * s]);
+            Phi[(int64_t)mu * count + k] = p * (pref * splus) + (1.0 - p) * (pref * sminus);
+        }
+    }
+    return FO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Jordan inversion with partial pivoting of an m x m row-major matrix. */
+static int invert(int m, const double* A, double* Ainv)
+{
+    double W[7][14];
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < 2 * m; ++c) W[r][c] = (c < m) ? A[r * m + c] : (c - m == r ? 1.0 : 0.0);
+    for (int c = 0; c < m; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < m; ++r)
+            if (fabs(W[r][c]) > fabs(W[piv][c])) piv = r;
+        if (W[piv][c] == 0.0) return FO_EINVAL;
+        if (piv != c)
+            for (int k = 0; k < 2 * m; ++k) {
+                double t = W[c][k];
+                W[c][k] = W[piv][k];
+                W[piv][k] = t;
+            }
+        const double d = W[c][c];
+        for (int k = 0; k < 2 * m; ++k) W[c][k] /= d;
+        for (int r = 0; r < m; ++r)
+            if (r != c) {
+                const double fct = W[r][c];
+                if (fct != 0.0)
+                    for (int k = 0; k < 2 * m; ++k) W[r][k] -= fct * W[c][k];
+            }
+    }
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) Ainv[r * m + c] = W[r][m + c];
+    return FO_OK;
+}
+
+/* Collision operator data.  MRT (Sec. 2.3): M of equation (MatrixD2); Lambda
+ * is the inverse of equation (MatrixS), whose flux block lambda-bar follows
+ * from equation (D_ab): D = e^2 (lambda-bar - Id/2) dx^2/dt.  BGK (Sec. 2.2):
+ * one relaxation time lambda from equation (Diffusion_Coefficient_3D), which
+ * needs an isotropic D. */
+typedef struct {
+    int Q, dim, collision;
+    double M[49], Minv[49], Lam[49], Laminv[49];
+    double lambda_bgk;
+} fo_collision;
+
+static const double M_D2Q5[25] = {
+    1, 1, 1, 1, 1,
+    0, 1, -1, 0, 0,
+    0, 0, 0, 1, -1,
+    4, -1, -1, -1, -1,
+    0, 1, 1, -1, -1,
+};
+static const double M_D3Q7[49] = {
+    1, 1, 1, 1, 1, 1, 1,
+    0, 1, -1, 0, 0, 0, 0,
+    0, 0, 0, 1, -1, 0, 0,
+    0, 0, 0, 0, 0, 1, -1,
+    6, -1, -1, -1, -1, -1, -1,
+    0, 2, 2, -1, -1, -1, -1,
+    0, 0, 0, 1, 1, -1, -1,
+};
+
+static int make_collision(const fo_problem* P, fo_collision* K)
+{
+    fo_lattice_t L;
+    int rc = validate(P);
+    if (rc) return rc;
+    lattice_of(P->dim, &L);
+    const int d = P->dim, Q = L.Q;
+    const double scale = P->dt / (L.e2 * P->dx * P->dx);
+    memset(K, 0, sizeof(*K));
+    K->Q = Q;
+    K->dim = d;
+    K->collision = P->collision;
+    if (P->collision == 0) {
+        /* BGK: D must be D*Id */
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                const double v = P->D[a * d + b];
+                if (a != b && v != 0.0) return FO_EINVAL;
+                if (a == b && v != P->D[0]) return FO_EINVAL;
+            }
+        K->lambda_bgk = P->D[0] * scale + 0.5;
+        if (!(K->lambda_bgk > 0.5)) return FO_EINVAL;
+        return FO_OK;
+    }
+    memcpy(K->M, d == 2 ? M_D2Q5 : M_D3Q7, sizeof(double) * Q * Q);
+    rc = invert(Q, K->M, K->Minv);
+    if (rc) return rc;
+    /* Lambda^{-1} = blockdiag(tau0, lambda-bar, tau_free...) */
+    K->Laminv[0] = P->tau0;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b)
+            K->Laminv[(1 + a) * Q + (1 + b)] = P->D[a * d + b] * scale + (a == b ? 0.5 : 0.0);
+    for (int k = d + 1; k < Q; ++k) K->Laminv[k * Q + k] = P->tau_free[k - d - 1];
+    /* lambda-bar - Id/2 must be symmetric positive definite (D SPD): check
+     * symmetry and leading principal minors of D. */
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < a; ++b)
+            if (P->D[a * d + b] != P->D[b * d + a]) return FO_EINVAL;
+    {
+        const double* D = P->D;
+        double m1 = D[0], m2, m3;
+        if (!(m1 > 0.0)) return FO_EINVAL;
+        m2 = D[0] * D[d + 1] - D[1] * D[d];
+        if (!(m2 > 0.0)) return FO_EINVAL;
+        if (d == 3) {
+            m3 = D[0] * (D[4] * D[8] - D[5] * D[7]) - D[1] * (D[3] * D[8] - D[5] * D[6]) +
+                 D[2] * (D[3] * D[7] - D[4] * D[6]);
+            if (!(m3 > 0.0)) return FO_EINVAL;
+        }
+    }
+    if (!(P->tau0 > 0.0)) return FO_EINVAL;
+    for (int k = d + 1; k < Q; ++k)
+        if (!(P->tau_free[k - d - 1] > 0.5)) return FO_EINVAL;
+    return invert(Q, K->Laminv, K->Lam);
+}
+
+int fo_collision_matrices(const fo_problem* P, double* M, double* Minv, double* Lam, double* lambda_bgk)
+{
+    fo_collision K;
+    int rc = make_collision(P, &K);
+    if (rc) return rc;
+    const int Q = 2 * P->dim + 1;
+    if (P->collision == 1) {
+        memcpy(M, K.M, sizeof(double) * Q * Q);
+        memcpy(Minv, K.Minv, sizeof(double) * Q * Q);
+        memcpy(Lam, K.Lam, sizeof(double) * Q * Q);
+    }
+    *lambda_bgk = K.lambda_bgk;
+    return FO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Equilibrium, equations (Feq) and (CoeffA_FADE3D), Sec. 2.2:
+ *   f^eq_0 = C - w0 sum_mu Phi_mu,
+ *   f^eq_i = w_i Phi_{mu(i)} + (C / e^2)(dt/dx) sum_mu u_mu e_{i,mu} w_i,
+ * where mu(i) is the axis of e_i (i = 2mu-1, 2mu). */
+static void equilibrium(const fo_problem* P, const fo_lattice_t* L, double C, const double* phi, double* feq)
+{
+    double sphi = 0.0;
+    for (int mu = 0; mu < P->dim; ++mu) sphi += phi[mu];
+    feq[0] = C - L->w[0] * sphi;
+    for (int i = 1; i < L->Q; ++i) {
+        const int mu = (i - 1) / 2;
+        double adv = 0.0;
+        for (int nu = 0; nu < P->dim; ++nu) adv += P->u[nu] * L->e[i][nu] * L->w[i];
+        feq[i] = L->w[i] * phi[mu] + (C / L->e2) * (P->dt / P->dx) * adv;
+    }
+}
+
+int fo_equilibrium(const fo_problem* P, double C, const double* phi, double* feq)
+{
+    fo_lattice_t L;
+    int rc = validate(P);
+    if (rc) return rc;
+    lattice_of(P->dim, &L);
+    equilibrium(P, &L, C, phi, feq);
+    return FO_OK;
+}
+
+/* Collision with source at one node, equation (MRT-Coll) (or (LBE_FADE) for
+ * BGK): f* = f - M^-1 Lambda M (f - f^eq) + w S dt. */
+static void collide(const fo_problem* P, const fo_lattice_t* L, const fo_collision* K,
+                    const double* f, const double* feq, double S, double* fstar)
+{
+    const int Q = L->Q;
+    if (K->collision == 0) {
+        for (int i = 0; i < Q; ++i)
+            fstar[i] = f[i] - (1.0 / K->lambda_bgk) * (f[i] - feq[i]) + L->w[i] * S * P->dt;
+        return;
+    }
+    double dev[7], m[7], lm[7];
+    for (int i = 0; i < Q; ++i) dev[i] = f[i] - feq[i];
+    for (int r = 0; r < Q; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < Q; ++c) s += K->M[r * Q + c] * dev[c];
+        m[r] = s;
+    }
+    for (int r = 0; r < Q; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < Q; ++c) s += K->Lam[r * Q + c] * m[c];
+        lm[r] = s;
+    }
+    for (int r = 0; r < Q; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < Q; ++c) s += K->Minv[r * Q + c] * lm[c];
+        fstar[r] = f[r] - s + L->w[r] * S * P->dt;
+    }
+}
+
+int fo_collide_node(const fo_problem* P, const double* f, double C, const double* phi, double S, double* fstar)
+{
+    fo_lattice_t L;
+    fo_collision K;
+    double feq[7];
+    int rc = make_collision(P, &K);
+    if (rc) return rc;
+    lattice_of(P->dim, &L);
+    equilibrium(P, &L, C, phi, feq);
+    collide(P, &L, &K, f, feq, S, fstar);
+    return FO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Moment C = <1|f> (Algorithm 1, last stage of the time loop). */
+int fo_moment(const fo_problem* P, const double* f, double* C)
+{
+    int rc = validate(P);
+    if (rc) return rc;
+    const int64_t nodes = nodes_of(P);
+    const int Q = 2 * P->dim + 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < nodes; ++x) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += f[(int64_t)i * nodes + x];
+        C[x] = s;
+    }
+    return FO_OK;
+}
+
+static int on_wall(const fo_problem* P, const int64_t x[3])
+{
+    for (int mu = 0; mu < P->dim; ++mu)
+        if (x[mu] == 0 || x[mu] == P->n[mu] - 1) return 1;
+    return 0;
+}
+
+/* Streaming, equation (Def_Translation): f_i(x + e_i dx, t + dt) = f*_i(x, t),
+ * taken as a pull f_i(y) = f*_i(y - e_i); a population whose source lies
+ * outside the domain is unknown.  Then the Dirichlet rule, equation
+ * (Dirichlet_BC) of Sec. 2.5: at a wall node with unknown set U,
+ * f_b = (C_wall - sum_{i not in U} f_i) / |U| for b in U (|U| = 1 on faces;
+ * the equal share at edges and corners is this implementation's reading). */
+static void stream_node(const fo_problem* P, const fo_lattice_t* L, const double* fstar,
+                        int64_t nodes, int64_t y, double* fy /* Q */)
+{
+    int64_t c[3];
+    coords_of(P, y, c);
+    int unknown[7] = {0}, nu_known = 0;
+    double known = 0.0;
+    for (int i = 0; i < L->Q; ++i) {
+        int inside = 1;
+        int64_t src = 0, mul = 1;
+        for (int mu = 0; mu < P->dim; ++mu) {
+            const int64_t s = c[mu] - L->e[i][mu];
+            if (s < 0 || s >= P->n[mu]) inside = 0;
+            src += s * mul;
+            mul *= P->n[mu];
+        }
+        if (inside) {
+            fy[i] = fstar[(int64_t)i * nodes + src];
+            known += fy[i];
+        } else {
+            unknown[i] = 1;
+            ++nu_known;
+        }
+    }
+    if (nu_known > 0) {
+        const double share = (P->c_wall - known) / (double)nu_known;
+        for (int i = 0; i < L->Q; ++i)
+            if (unknown[i]) fy[i] = share;
+    }
+}
+
+/* Initial state (Algorithm 1, initialisations; reading: f(x, 0) is the
+ * equilibrium of the initial concentration whose wall nodes carry C_wall). */
+int fo_init(const fo_problem* P, const double* C0, double* f)
+{
+    fo_lattice_t L;
+    int rc = validate(P);
+    if (rc) return rc;
+    lattice_of(P->dim, &L);
+    const int64_t nodes = nodes_of(P);
+    double* C = (double*)malloc(sizeof(double) * nodes);
+    double* Phi = (double*)malloc(sizeof(double) * nodes * P->dim);
+    if (!C || !Phi) {
+        free(C);
+        free(Phi);
+        return FO_ENOMEM;
+    }
+    for (int64_t x = 0; x < nodes; ++x) {
+        int64_t c[3];
+        coords_of(P, x, c);
+        C[x] = on_wall(P, c) ? P->c_wall : C0[x];
+    }
+    rc = fo_phi(P, C, Phi);
+    if (!rc) {
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < nodes; ++x) {
+            double phi[3], feq[7];
+            for (int mu = 0; mu < P->dim; ++mu) phi[mu] = Phi[(int64_t)mu * nodes + x];
+            equilibrium(P, &L, C[x], phi, feq);
+            for (int i = 0; i < L.Q; ++i) f[(int64_t)i * nodes + x] = feq[i];
+        }
+    }
+    free(C);
+    free(Phi);
+    return rc;
+}
+
+/* Collision at every node: f -> f* (stages 1-2 of the time loop plus the
+ * right-hand side of (MRT-Coll)).  C is the moment of f at the start of the
+ * step. */
+static int collide_all(const fo_problem* P, const fo_lattice_t* L, const fo_collision* K,
+                       const double* f, const double* S, double* fstar)
+{
+    const int64_t nodes = nodes_of(P);
+    double* C = (double*)malloc(sizeof(double) * nodes);
+    double* Phi = (double*)malloc(sizeof(double) * nodes * P->dim);
+    int rc = FO_ENOMEM;
+    if (C && Phi) {
+        fo_moment(P, f, C);
+        rc = fo_phi(P, C, Phi);
+        if (!rc) {
+#pragma omp parallel for schedule(static)
+            for (int64_t x = 0; x < nodes; ++x) {
+                double fx[7], phi[3], feq[7], fs[7];
+                for (int i = 0; i < L->Q; ++i) fx[i] = f[(int64_t)i * nodes + x];
+                for (int mu = 0; mu < P->dim; ++mu) phi[mu] = Phi[(int64_t)mu * nodes + x];
+                equilibrium(P, L, C[x], phi, feq);
+                collide(P, L, K, fx, feq, S ? S[x] : 0.0, fs);
+                for (int i = 0; i < L->Q; ++i) fstar[(int64_t)i * nodes + x] = fs[i];
+            }
+        }
+    }
+    free(C);
+    free(Phi);
+    return rc;
+}
+
+/* nsteps iterations of the time loop of Algorithm 1 on f in place.
+ * S may be NULL (no source). */
+int fo_step(const fo_problem* P, double* f, const double* S, int64_t nsteps)
+{
+    fo_lattice_t L;
+    fo_collision K;
+    int rc = make_collision(P, &K);
+    if (rc) return rc;
+    if (nsteps < 0) return FO_EINVAL;
+    lattice_of(P->dim, &L);
+    const int64_t nodes = nodes_of(P);
+    double* fstar = (double*)malloc(sizeof(double) * nodes * L.Q);
+    if (!fstar) return FO_ENOMEM;
+    for (int64_t m = 0; m < nsteps && !rc; ++m) {
+        rc = collide_all(P, &L, &K, f, S, fstar);
+        if (rc) break;
+#pragma omp parallel for schedule(static)
+        for (int64_t y = 0; y < nodes; ++y) {
+            double fy[7];
+            stream_node(P, &L, fstar, nodes, y, fy);
+            for (int i = 0; i < L.Q; ++i) f[(int64_t)i * nodes + y] = fy[i];
+        }
+    }
+    free(fstar);
+    return rc;
+}
+
+/* One iteration of the time loop evaluated only at the listed nodes: given
+ * the full state f at time t, returns f(t + dt) at those nodes,
+ * fnew[i*count + k].  Needs C(t) everywhere (cheap) but Phi only at the
+ * listed nodes and their lattice neighbours. */
+int fo_step_sampled(const fo_problem* P, const double* f, const double* S,
+                    const int64_t* which, int64_t count, double* fnew)
+{
+    fo_lattice_t L;
+    fo_collision K;
+    int rc = make_collision(P, &K);
+    if (rc) return rc;
+    lattice_of(P->dim, &L);
+    const int64_t nodes = nodes_of(P);
+    const int Q = L.Q;
+    for (int64_t k = 0; k < count; ++k)
+        if (which[k] < 0 || which[k] >= nodes) return FO_EINVAL;
+    double* C = (double*)malloc(sizeof(double) * nodes);
+    int64_t* src = (int64_t*)malloc(sizeof(int64_t) * count * Q);
+    double* phi = (double*)malloc(sizeof(double) * count * Q * P->dim);
+    if (!C || !src || !phi) {
+        free(C);
+        free(src);
+        free(phi);
+        return FO_ENOMEM;
+    }
+    fo_moment(P, f, C);
+    /* source node of every population of every listed node (or -1) */
+    for (int64_t k = 0; k < count; ++k) {
+        int64_t c[3];
+        coords_of(P, which[k], c);
+        for (int i = 0; i < Q; ++i) {
+            int inside = 1;
+            int64_t s_idx = 0, mul = 1;
+            for (int mu = 0; mu < P->dim; ++mu) {
+                const int64_t s = c[mu] - L.e[i][mu];
+                if (s < 0 || s >= P->n[mu]) inside = 0;
+                s_idx += s * mul;
+                mul *= P->n[mu];
+            }
+            src[k * Q + i] = inside ? s_idx : -1;
+        }
+    }
+    /* Phi at the source nodes (an outside source gets a dummy index 0) */
+    {
+        int64_t* at = (int64_t*)malloc(sizeof(int64_t) * count * Q);
+        if (!at) rc = FO_ENOMEM;
+        else {
+            for (int64_t j = 0; j < count * Q; ++j) at[j] = src[j] >= 0 ? src[j] : 0;
+            rc = fo_phi_at(P, C, at, count * Q, phi);
+            free(at);
+        }
+    }
+    if (!rc) {
+        for (int64_t k = 0; k < count; ++k) {
+            int unknown[7] = {0}, nu = 0;
+            double known = 0.0, fy[7];
+            for (int i = 0; i < Q; ++i) {
+                const int64_t s = src[k * Q + i];
+                if (s < 0) {
+                    unknown[i] = 1;
+                    ++nu;
+                    continue;
+                }
+                double fs[7], ph[3], feq[7], fst[7];
+                for (int j = 0; j < Q; ++j) fs[j] = f[(int64_t)j * nodes + s];
+                for (int mu = 0; mu < P->dim; ++mu) ph[mu] = phi[(int64_t)mu * count * Q + k * Q + i];
+                equilibrium(P, &L, C[s], ph, feq);
+                collide(P, &L, &K, fs, feq, S ? S[s] : 0.0, fst);
+                fy[i] = fst[i];
+                known += fy[i];
+            }
+            if (nu > 0) {
+                const double share = (P->c_wall - known) / (double)nu;
+                for (int i = 0; i < Q; ++i)
+                    if (unknown[i]) fy[i] = share;
+            }
+            for (int i = 0; i < Q; ++i) fnew[(int64_t)i * count + k] = fy[i];
+        }
+    }
+    free(C);
+    free(src);
+    free(phi);
+    return rc;
+}

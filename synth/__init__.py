@@ -1,0 +1,148 @@
+"""Seeded synthetic workloads shared by the oracle side and the GPU side.
+
+This module holds configuration data (grid, lattice, fractional orders,
+skewness, diffusion tensor, velocity, relaxation times) and seeded generators
+of initial concentrations and sources.  It contains none of the method's
+arithmetic: no fractional weights, no equilibrium, no relaxation, no
+streaming.  The workload shapes follow the paper's tests: Gaussian plumes in a
+square or cubic box with homogeneous Dirichlet walls (Sec. 3.2, Gaussian hill
+initial condition), written here in lattice units (dx = dt = 1).
+
+Readings used for every workload (the paper fixes none of them in lattice
+units): g = 1 on every axis, every free relaxation time = 1, the relaxation
+time of the mass moment = 1 (it has no effect), wall value 0.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+_COMMON = dict(dx=1.0, dt=1.0, collision="MRT", tau_free=[1.0, 1.0, 1.0, 1.0], tau0=1.0, c_wall=0.0)
+
+
+def _rot30_D(l1: float, l2: float):
+    """R(+30 deg) diag(l1, l2) R(+30 deg)^T: a rotated anisotropic tensor."""
+    c, s = math.cos(math.pi / 6), math.sin(math.pi / 6)
+    R = np.array([[c, -s], [s, c]])
+    D = R @ np.diag([l1, l2]) @ R.T
+    return (0.5 * (D + D.T)).tolist()
+
+
+CONFIGS = {
+    # small case the oracle finishes in seconds
+    "c1_64sq": dict(_COMMON, dim=2, n=[64, 64], steps=200, alpha=[1.5, 1.5], p=[0.5, 0.5], g=[1.0, 1.0],
+                    D=[[0.1, 0.0], [0.0, 0.1]], u=[0.0, 0.0],
+                    init=dict(kind="gauss", sigma=3.0, center=[31.5, 31.5], amp=1.0)),
+    # the benchmark workload
+    "c2_1024sq": dict(_COMMON, dim=2, n=[1024, 1024], steps=2000, alpha=[1.3, 1.7], p=[0.3, 0.8], g=[1.0, 1.0],
+                      D=_rot30_D(0.05, 0.2), u=[0.05, 0.02],
+                      init=dict(kind="pulses", count=8, sigma=[4.0, 20.0], amp=[0.5, 1.0], seed=2)),
+    "c3_256cube": dict(_COMMON, dim=3, n=[256, 256, 256], steps=500, alpha=[1.5, 1.6, 1.8], p=[0.5, 0.2, 0.9],
+                       g=[1.0, 1.0, 1.0], D=[[0.1, 0, 0], [0, 0.05, 0], [0, 0, 0.02]], u=[0.03, 0.0, 0.0],
+                       init=dict(kind="gauss", sigma=6.0, center=[127.5, 127.5, 127.5], amp=1.0),
+                       source=dict(kind="point", node=[64, 128, 128], value=1e-3)),
+    "c4_4096sq": dict(_COMMON, dim=2, n=[4096, 4096], steps=1000, alpha=[1.2, 1.9], p=[1.0, 0.0], g=[1.0, 1.0],
+                      D=[[0.1, 0.0], [0.0, 0.1]], u=[0.02, 0.02],
+                      init=dict(kind="pulses", count=8, sigma=[4.0, 20.0], amp=[0.5, 1.0], seed=4)),
+    # adjoint workload: hidden parameters that generate the observed plume ...
+    "c5_512sq_hidden": dict(_COMMON, dim=2, n=[512, 512], steps=500, alpha=[1.6, 1.4], p=[0.6, 0.4], g=[1.0, 1.0],
+                            D=[[0.08, 0.03], [0.03, 0.15]], u=[0.04, -0.01], ckpt_every=50,
+                            init=dict(kind="pulses", count=8, sigma=[4.0, 20.0], amp=[0.5, 1.0], seed=5)),
+    # ... and the point at which the gradient is evaluated
+    "c5_512sq_eval": dict(_COMMON, dim=2, n=[512, 512], steps=500, alpha=[1.6, 1.4], p=[0.5, 0.5], g=[1.0, 1.0],
+                          D=[[0.1, 0.0], [0.0, 0.1]], u=[0.0, 0.0], ckpt_every=50,
+                          init=dict(kind="pulses", count=8, sigma=[4.0, 20.0], amp=[0.5, 1.0], seed=5)),
+}
+
+
+def config(name: str, **overrides) -> dict:
+    """A deep copy of a named configuration with optional overrides."""
+    cfg = copy.deepcopy(CONFIGS[name])
+    cfg["name"] = name
+    cfg.update(copy.deepcopy(overrides))
+    return cfg
+
+
+def shape(cfg: dict):
+    """Array shape of a node field, slowest axis first: (ny, nx) or (nz, ny, nx)."""
+    return tuple(int(v) for v in reversed(cfg["n"][: cfg["dim"]]))
+
+
+def nodes(cfg: dict) -> int:
+    return int(np.prod(cfg["n"][: cfg["dim"]]))
+
+
+def _coords(cfg: dict):
+    d = cfg["dim"]
+    axes = [np.arange(cfg["n"][mu], dtype=np.float64) for mu in range(d)]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")  # slowest first
+    return list(reversed(grids))  # grids[mu] = coordinate along axis mu
+
+
+def gaussian(cfg: dict, center, sigma: float, amp: float = 1.0) -> np.ndarray:
+    """Peak-amp Gaussian hill (the paper's initial condition, Sec. 3.2) in node units."""
+    X = _coords(cfg)
+    r2 = sum((X[mu] - center[mu]) ** 2 for mu in range(cfg["dim"]))
+    return amp * np.exp(-0.5 * r2 / sigma**2)
+
+
+def initial_C(cfg: dict) -> np.ndarray:
+    """Seeded initial concentration in FP64, shape ``shape(cfg)``."""
+    spec = cfg["init"]
+    if spec["kind"] == "gauss":
+        return gaussian(cfg, spec["center"], spec["sigma"], spec.get("amp", 1.0))
+    if spec["kind"] == "pulses":
+        rng = np.random.default_rng(spec["seed"])
+        C = np.zeros(shape(cfg))
+        for _ in range(spec["count"]):
+            sig = rng.uniform(*spec["sigma"])
+            amp = rng.uniform(*spec["amp"])
+            ctr = [rng.uniform(3 * sig, cfg["n"][mu] - 1 - 3 * sig) for mu in range(cfg["dim"])]
+            C += gaussian(cfg, ctr, sig, amp)
+        return C
+    if spec["kind"] == "random":
+        rng = np.random.default_rng(spec["seed"])
+        return rng.uniform(spec.get("low", 0.0), spec.get("high", 1.0), size=shape(cfg))
+    raise ValueError(spec["kind"])
+
+
+def source(cfg: dict):
+    """Constant-in-time source field S (FP64) or None."""
+    spec = cfg.get("source")
+    if not spec:
+        return None
+    S = np.zeros(shape(cfg))
+    if spec["kind"] == "point":
+        idx = tuple(reversed(spec["node"]))
+        S[idx] = spec["value"]
+        return S
+    if spec["kind"] == "random":
+        rng = np.random.default_rng(spec["seed"])
+        return rng.uniform(-spec["scale"], spec["scale"], size=shape(cfg))
+    raise ValueError(spec["kind"])
+
+
+def small(dim: int, n, *, seed: int = 0, collision: str = "MRT", alpha=None, p=None, D=None, u=None,
+          with_source: bool = False, **kw) -> dict:
+    """A small random test problem (several GEMM tiles plus a ragged tail when n is odd-sized)."""
+    rng = np.random.default_rng(seed)
+    d = dim
+    cfg = dict(_COMMON, dim=d, n=list(n), steps=kw.pop("steps", 10), collision=collision,
+               alpha=list(alpha) if alpha is not None else list(rng.uniform(1.2, 1.95, d)),
+               p=list(p) if p is not None else list(rng.uniform(0.0, 1.0, d)),
+               g=[1.0] * d,
+               u=list(u) if u is not None else list(rng.uniform(-0.03, 0.03, d)),
+               init=dict(kind="random", seed=seed + 1000, low=0.0, high=1.0))
+    if D is None:
+        A = rng.uniform(-0.03, 0.03, (d, d))
+        D = (np.diag(rng.uniform(0.05, 0.2, d)) + 0.5 * (A + A.T)).tolist()
+        if collision == "BGK":
+            v = float(rng.uniform(0.05, 0.2))
+            D = (v * np.eye(d)).tolist()
+    cfg["D"] = D
+    if with_source:
+        cfg["source"] = dict(kind="random", seed=seed + 2000, scale=1e-3)
+    cfg.update(kw)
+    return cfg
