@@ -1,0 +1,167 @@
+/*
+ * lbm_fade.h -- C ABI of the MI355X (gfx950) library that runs the time step
+ * of the lattice Boltzmann (LB) scheme for the space-fractional
+ * advection-diffusion equation (FADE) of Cartalade, Younsi and Neel,
+ * "Multiple-Relaxation-Time Lattice Boltzmann scheme for Fractional
+ * Advection-Diffusion Equation" (arXiv:1706.09161).
+ *
+ * One step (Algorithm 1, time loop) is, on device:
+ *   Phi_mu = p_mu I+^{2-alpha_mu}(g_mu C) + (1-p_mu) I-^{2-alpha_mu}(g_mu C) along every
+ *            grid line of every axis (Sec. 2.4, trapezoidal product rule), run as
+ *            a Toeplitz-plus-boundary-column GEMM on the matrix cores;
+ *   f^eq(C, Phi, u) (Sec. 2.2, equations (Feq), (CoeffA_FADE3D));
+ *   BGK or MRT collision with source (equations (LBE_FADE), (MRT-Coll));
+ *   streaming (equation (Def_Translation)) and the Dirichlet rule
+ *   (equation (Dirichlet_BC)); the new moment C = <1|f>.
+ *
+ * Conventions
+ *   - Every call returns 0 (LBM_OK) or a negative LBM_E* code and never throws.
+ *     lbm_fade_last_error() gives a message for the calling thread's last failure.
+ *   - Grids count nodes per axis INCLUDING both wall nodes (the paper's N_mu + 1).
+ *     Node fields are dense, x fastest: index x + nx*(y + ny*z).  Populations are
+ *     structure-of-arrays: f[i*nodes + node], i = 0..Q-1 in the paper's order
+ *     (e_0 = 0, e_{2mu-1} = +b_mu, e_{2mu} = -b_mu).
+ *   - Pointers marked "host or device" are device pointers when on_device != 0
+ *     (they must be on the handle's device and ordered on `stream`), else host
+ *     pointers.  They are only borrowed for the duration of the call.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls are
+ *     asynchronous on it unless stated otherwise; a call that reads into host
+ *     memory synchronises the stream before returning.
+ *   - The library owns all device state (populations, C, Phi, weights,
+ *     checkpoints).  A handle is not thread-safe; distinct handles are.
+ *   - On error the handle's state is unchanged unless stated otherwise.
+ */
+#ifndef LBM_FADE_H
+#define LBM_FADE_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LBM_API __attribute__((visibility("default")))
+#else
+#define LBM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_fade* lbm_fade_t;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument or parameter */
+    LBM_ENOMEM = -2,     /* device or host allocation failed */
+    LBM_EDEVICE = -3,    /* HIP runtime error, or no usable gfx950 device */
+    LBM_ENONFINITE = -4, /* non-finite value found by the optional guard */
+    LBM_ESTATE = -5      /* call out of order (e.g. step before set_C) */
+};
+
+enum { LBM_D2Q5 = 5, LBM_D3Q7 = 7 };
+enum { LBM_BGK = 0, LBM_MRT = 1 };
+
+/* Arithmetic of the fractional-term GEMM.  Weights are always generated in FP64.
+ *   LBM_FP32   FP32 operands on FP32 MFMA, FP32 accumulation;
+ *   LBM_BF16X3 3-term split BF16: W = W_hi + W_lo, C = C_hi + C_lo (round to
+ *              nearest even), W_hi C_hi + W_hi C_lo + W_lo C_hi on BF16 MFMA with
+ *              FP32 accumulation (the lo*lo term is dropped);
+ *   LBM_FP32_SIMT  FP32 fused multiply-add on the vector units (no MFMA); a
+ *              plain kernel kept as a second implementation of the operator. */
+enum { LBM_FP32 = 0, LBM_BF16X3 = 1, LBM_FP32_SIMT = 2 };
+
+typedef struct {
+    int32_t dim;   /* 2 or 3 */
+    int32_t n[3];  /* nodes per axis incl. both walls (>= 3); n[2] ignored in 2D */
+    double dx, dt; /* lattice spacing and time step (> 0) */
+} lbm_grid;
+
+typedef struct {
+    double alpha[3];    /* fractional orders, in (1, 2]; gamma_mu = 2 - alpha_mu (Sec. 1) */
+    double p[3];        /* skewness weights, in [0, 1] */
+    double g[3];        /* positive factors g_mu (uniform per axis) */
+    double D[9];        /* d x d diffusion tensor, row-major, symmetric positive definite */
+    double u[3];        /* uniform velocity */
+    double tau_free[4]; /* MRT relaxation TIMES of the moments beyond the fluxes (> 1/2):
+                           D2Q5 rows 3,4 of M; D3Q7 rows 4,5,6 (Sec. 2.3).  Ignored for BGK. */
+    double tau0;        /* relaxation time of the mass moment (> 0; no effect, Sec. 2.3) */
+    double c_wall;      /* Dirichlet value on every wall node (Sec. 2.5) */
+    int32_t collision;  /* LBM_BGK (needs isotropic D) or LBM_MRT */
+    int32_t precision;  /* LBM_FP32, LBM_BF16X3 or LBM_FP32_SIMT */
+    int32_t nonfinite_check_every; /* 0 = off; else check C every k steps inside lbm_fade_step */
+    int32_t reserved;
+} lbm_params;
+
+/* Create a solver on the current HIP device.  Computes in FP64 on the host:
+ * the relaxation times lambda-bar = D dt/(e^2 dx^2) + Id/2 (equation (D_ab);
+ * for BGK equation (Diffusion_Coefficient_3D)) and the collision matrix
+ * M^-1 Lambda M (equations (MatrixD2), (MatrixS)); the product-rule weights
+ * c+-_{ln}(gamma_mu) of equations (c+), (c-) scaled by dx^gamma/Gamma(2+gamma),
+ * as one Toeplitz generator per axis plus two boundary columns.
+ * Allocates the device state (two population buffers, C, Phi, weights).
+ * Errors: LBM_EINVAL for alpha outside (1,2], p outside [0,1], g <= 0, D not SPD
+ * (or not isotropic for BGK), tau_free <= 1/2, tau0 <= 0, n < 3, lattice != 2*dim+1,
+ * unknown collision/precision; LBM_EDEVICE if the current device is not gfx950.
+ * On error *out is set to NULL. */
+LBM_API int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* params, lbm_fade_t* out);
+
+/* Destroy a handle and free its device memory (NULL-safe; synchronises the device). */
+LBM_API void lbm_fade_destroy(lbm_fade_t h);
+
+/* Set the initial concentration (host or device, nodes floats).  Wall nodes are
+ * overwritten with c_wall, Phi(C0) is computed, and f := f^eq(C0, Phi(C0))
+ * (reading of Algorithm 1's initialisations: the paper does not fix f(x, 0)). */
+LBM_API int lbm_fade_set_C(lbm_fade_t h, const float* C0, int32_t on_device, void* stream);
+
+/* Set a constant-in-time source field S (host or device, nodes floats), added as
+ * w_i S dt after collision (equation (LBE_FADE)); NULL removes the source. */
+LBM_API int lbm_fade_set_source(lbm_fade_t h, const float* S, int32_t on_device, void* stream);
+
+/* Advance n >= 0 time steps.  Asynchronous; the launches of one step are: the
+ * fractional-term GEMM of every axis, then the fused collide-stream-boundary-
+ * moment kernel.  Returns LBM_ESTATE before set_C/set_f. */
+LBM_API int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream);
+
+/* Copy C (nodes floats) to host or device memory. */
+LBM_API int lbm_fade_get_C(lbm_fade_t h, float* dst, int32_t on_device, void* stream);
+
+/* Copy / replace the populations (Q*nodes floats, structure of arrays) of the
+ * current state (after streaming and the Dirichlet rule).  set_f recomputes C. */
+LBM_API int lbm_fade_get_f(lbm_fade_t h, float* dst, int32_t on_device, void* stream);
+LBM_API int lbm_fade_set_f(lbm_fade_t h, const float* src, int32_t on_device, void* stream);
+
+/* Apply the fractional operator of Sec. 2.4 to a given field:
+ * Phi[mu*nodes + node] = p_mu I+(g_mu C) + (1-p_mu) I-(g_mu C) for every axis,
+ * with the handle's precision.  C and Phi are host or device (same on_device).
+ * Does not touch the solver state. */
+LBM_API int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t on_device, void* stream);
+
+/* Gradients reported by lbm_fade_adjoint (FP64). */
+typedef struct {
+    double dD[9]; /* d x d, symmetric: d/dD_ab of the loss with D_ab = D_ba tied */
+    double du[3];
+    double dp[3];
+} lbm_grads;
+
+/* Vector-Jacobian product of n steps (a hand-written adjoint; the paper has
+ * none).  With C_n the concentration after n steps from the state given by
+ * set_C (and the source given by set_source), returns the gradients of
+ * L = <gC, C_n> with respect to D, u, p, the initial concentration (dC0, wall
+ * entries zero; nullable) and the constant source (dS; nullable).  gC, dC0
+ * and dS are host or device (same on_device), nodes floats each.  The forward
+ * states are checkpointed every ckpt_every steps and recomputed per segment.
+ * The solver state after the call is the state after n steps.  Synchronises
+ * `stream` (the scalar gradients are written to host memory). */
+LBM_API int lbm_fade_adjoint(lbm_fade_t h, int64_t n, int32_t ckpt_every, const float* gC, int32_t on_device,
+                     lbm_grads* out, float* dC0, float* dS, void* stream);
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+LBM_API const char* lbm_fade_last_error(void);
+
+/* Library version string. */
+LBM_API const char* lbm_fade_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_FADE_H */

@@ -81,6 +81,7 @@ def lib():
             "fo_init": (ctypes.c_int, [P, dp, dp]),
             "fo_step": (ctypes.c_int, [P, dp, dp, ctypes.c_int64]),
             "fo_step_sampled": (ctypes.c_int, [P, dp, dp, ip, ctypes.c_int64, dp]),
+            "fo_threads": (ctypes.c_int, []),
         }
         if hasattr(L, "fo_adjoint"):
             sig["fo_adjoint"] = (ctypes.c_int, [P, dp, dp, ctypes.c_int64, dp, dp, dp, dp, dp, dp])
@@ -249,6 +250,11 @@ def step_sampled(cfg: dict, f: np.ndarray, nodes: np.ndarray, S: np.ndarray | No
     out = np.zeros((Q_of(cfg), nodes.size))
     _check(lib().fo_step_sampled(ctypes.byref(P), _dp(f), Sp, _ip(nodes), nodes.size, _dp(out)), "step_sampled")
     return out
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP)."""
+    return int(lib().fo_threads())
 
 
 def run(cfg: dict, C0: np.ndarray, nsteps: int, S: np.ndarray | None = None) -> np.ndarray:

@@ -734,3 +734,16 @@ int fo_step_sampled(const fo_problem* P, const double* f, const double* S,
     free(phi);
     return rc;
 }
+
+/* Number of threads the parallel loops above use. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int fo_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,402 @@
+// collide_stream.hip -- equilibrium, collision, streaming, Dirichlet rule and
+// moment of one LB time step, fused into one pass over the populations
+// (Algorithm 1, time-loop stages 2-5; Sec. 2.2, 2.3, 2.5).
+//
+// State between steps: populations f after streaming and the Dirichlet rule,
+// and their moment C = <1|f> (written by this kernel for the next step's
+// fractional term).  For every node x the kernel
+//   1. recomputes C(x) = sum_i f_i(x),
+//   2. builds f^eq(C, Phi, u) (equations (Feq), (CoeffA_FADE3D)),
+//   3. collides: f* = f - R (f - f^eq) + w S dt with R = M^-1 Lambda M
+//      (equation (MRT-Coll); BGK: R = I / lambda, equation (LBE_FADE)),
+//   4. and the new populations are pulled: f_i(x) <- f*_i(x - e_i)
+//      (equation (Def_Translation)); a population whose source lies outside
+//      the box is unknown and the Dirichlet rule (Dirichlet_BC) sets it:
+//      f_b = (C_wall - sum of the known) / |unknown| (equal share at edges and
+//      corners);
+//   5. and writes the new f and C = sum_i f_i.
+//
+// 2D (D2Q5): each wavefront owns a strip of 64 columns (62 outputs plus one
+// halo column per side, whose f*_1 / f*_2 reach the neighbours through lane
+// shuffles) and marches up the y axis: the collision of row y+1 is computed
+// once, its f*_4 is used for row y and its f*_3 for row y+2.  Every node is
+// collided once (plus 2 halo columns per 62 and 2 halo rows per chunk), every
+// population is read once and written once: (2Q + d + 1) * 4 bytes per node
+// from HBM (52 B for D2Q5).
+//
+// 3D (D3Q7): a workgroup of NY wavefronts covers 64 x NY nodes of one z plane
+// (one wave per y row, rows 0 and NY-1 halo) and marches along z; f*_3/f*_4
+// cross rows through LDS, f*_5/f*_6 cross planes in registers.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kStrip = 62;  // output columns per wavefront (64 lanes minus 2 halo)
+
+template <int Q>
+__device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
+                                    float S, float (&fs)[Q])
+{
+    constexpr int d = (Q - 1) / 2;
+    float C = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) C += f[i];
+    float feq[Q];
+    float sphi = 0.f;
+#pragma unroll
+    for (int mu = 0; mu < d; ++mu) sphi += phi[mu];
+    feq[0] = C - cc.w[0] * sphi;
+#pragma unroll
+    for (int mu = 0; mu < d; ++mu) {
+        const float a = cc.w[2 * mu + 1] * phi[mu];
+        const float b = cc.adv[mu] * C;
+        feq[2 * mu + 1] = a + b;
+        feq[2 * mu + 2] = a - b;
+    }
+    float dev[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dev[i] = f[i] - feq[i];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        float r = 0.f;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) r = fmaf(cc.R[i * Q + j], dev[j], r);
+        fs[i] = f[i] - r;
+        fs[i] = fmaf(cc.wSdt[i], S, fs[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D D2Q5 fused kernel.
+template <bool HAS_S>
+__global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
+                                                         float* __restrict__ fout, const float* __restrict__ Phi,
+                                                         const float* __restrict__ S, float* __restrict__ Cout,
+                                                         int rows_per_wave, int strips, int total_waves)
+{
+    const int nx = cc.n[0], ny = cc.n[1];
+    const int64_t nodes = (int64_t)nx * ny;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gw >= total_waves) return;  // whole wavefront exits together
+    const int strip = gw % strips, chunk = gw / strips;
+    const int x = strip * kStrip - 1 + lane;
+    const bool col_ok = (x >= 0) && (x < nx);
+    const bool out_lane = col_ok && lane >= 1 && lane <= kStrip;
+    const int y0 = chunk * rows_per_wave;
+    const int y1 = min(ny, y0 + rows_per_wave);
+
+    auto collide_row = [&](int y, float (&fs)[5]) {
+        float f[5], phi[2], s = 0.f;
+        if (col_ok) {
+            const int64_t node = (int64_t)y * nx + x;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) f[i] = fin[i * nodes + node];
+            phi[0] = Phi[node];
+            phi[1] = Phi[nodes + node];
+            if (HAS_S) s = S[node];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) f[i] = 0.f;
+            phi[0] = phi[1] = 0.f;
+        }
+        collide_node<5>(cc, f, phi, s, fs);
+    };
+
+    float prev3 = 0.f;
+    float cur[5], nxt[5];
+    if (y0 >= 1) {
+        float t[5];
+        collide_row(y0 - 1, t);
+        prev3 = t[3];
+    }
+    collide_row(y0, cur);
+    for (int y = y0; y < y1; ++y) {
+        const bool has_next = (y + 1 < ny);
+        if (has_next) {
+            collide_row(y + 1, nxt);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) nxt[i] = 0.f;
+        }
+        // pull: f_1 from x-1, f_2 from x+1 (lane shuffles), f_3 from y-1, f_4 from y+1
+        const float from_left = __shfl_up(cur[1], 1, 64);
+        const float from_right = __shfl_down(cur[2], 1, 64);
+        float f[5] = {cur[0], from_left, from_right, prev3, nxt[4]};
+        bool unk[5] = {false, x == 0, x == nx - 1, y == 0, y == ny - 1};
+        int nu = 0;
+        float known = 0.f;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            if (unk[i]) ++nu;
+            else known += f[i];
+        }
+        if (nu > 0) {
+            const float share = (cc.c_wall - known) / (float)nu;
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                if (unk[i]) f[i] = share;
+        }
+        if (out_lane) {
+            const int64_t node = (int64_t)y * nx + x;
+            float c = 0.f;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                fout[i * nodes + node] = f[i];
+                c += f[i];
+            }
+            Cout[node] = c;
+        }
+        prev3 = cur[3];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) cur[i] = nxt[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D D3Q7 fused kernel: workgroup = NY wavefronts (one per y row), rows 0 and
+// NY-1 of the workgroup are halo rows; marches along z.
+template <int NY, bool HAS_S>
+__global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, const float* __restrict__ fin,
+                                                             float* __restrict__ fout, const float* __restrict__ Phi,
+                                                             const float* __restrict__ S, float* __restrict__ Cout,
+                                                             int planes_per_block, int strips_x, int strips_y)
+{
+    const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t nodes = plane * nz;
+    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+    int b = blockIdx.x;
+    const int sx = b % strips_x;
+    b /= strips_x;
+    const int sy = b % strips_y;
+    const int chunk = b / strips_y;
+    const int x = sx * kStrip - 1 + lane;
+    const int y = sy * (NY - 2) - 1 + row;
+    const bool ok = (x >= 0) && (x < nx) && (y >= 0) && (y < ny);
+    const bool out = ok && lane >= 1 && lane <= kStrip && row >= 1 && row <= NY - 2;
+    const int z0 = chunk * planes_per_block;
+    const int z1 = min(nz, z0 + planes_per_block);
+
+    // f*_3 (moving +y) and f*_4 (moving -y) of the current plane, exchanged between rows
+    __shared__ float sh3[NY][64];
+    __shared__ float sh4[NY][64];
+
+    auto collide_at = [&](int z, float (&fs)[7]) {
+        float f[7], phi[3], s = 0.f;
+        if (ok) {
+            const int64_t node = (int64_t)z * plane + (int64_t)y * nx + x;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) f[i] = fin[i * nodes + node];
+#pragma unroll
+            for (int mu = 0; mu < 3; ++mu) phi[mu] = Phi[mu * nodes + node];
+            if (HAS_S) s = S[node];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) f[i] = 0.f;
+            phi[0] = phi[1] = phi[2] = 0.f;
+        }
+        collide_node<7>(cc, f, phi, s, fs);
+    };
+
+    float prev5 = 0.f;
+    float cur[7], nxt[7];
+    if (z0 >= 1) {
+        float t[7];
+        collide_at(z0 - 1, t);
+        prev5 = t[5];
+    }
+    collide_at(z0, cur);
+    for (int z = z0; z < z1; ++z) {
+        const bool has_next = (z + 1 < nz);
+        if (has_next) {
+            collide_at(z + 1, nxt);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) nxt[i] = 0.f;
+        }
+        sh3[row][lane] = cur[3];
+        sh4[row][lane] = cur[4];
+        __syncthreads();
+        const float from_left = __shfl_up(cur[1], 1, 64);
+        const float from_right = __shfl_down(cur[2], 1, 64);
+        const float from_below = row >= 1 ? sh3[row - 1][lane] : 0.f;   // f*_3 of y-1
+        const float from_above = row + 1 < NY ? sh4[row + 1][lane] : 0.f;  // f*_4 of y+1
+        float f[7] = {cur[0], from_left, from_right, from_below, from_above, prev5, nxt[6]};
+        bool unk[7] = {false, x == 0, x == nx - 1, y == 0, y == ny - 1, z == 0, z == nz - 1};
+        int nu = 0;
+        float known = 0.f;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            if (unk[i]) ++nu;
+            else known += f[i];
+        }
+        if (nu > 0) {
+            const float share = (cc.c_wall - known) / (float)nu;
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                if (unk[i]) f[i] = share;
+        }
+        if (out) {
+            const int64_t node = (int64_t)z * plane + (int64_t)y * nx + x;
+            float c = 0.f;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+                fout[i * nodes + node] = f[i];
+                c += f[i];
+            }
+            Cout[node] = c;
+        }
+        __syncthreads();  // sh3/sh4 are rewritten in the next plane
+        prev5 = cur[5];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// f := f^eq(C, Phi) at every node (initial state).
+template <int Q>
+__global__ void equilibrium_init(CollideConsts cc, const float* __restrict__ C, const float* __restrict__ Phi,
+                                 float* __restrict__ f, int64_t nodes)
+{
+    constexpr int d = (Q - 1) / 2;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nodes) return;
+    const float c = C[x];
+    float sphi = 0.f;
+    float phi[d];
+#pragma unroll
+    for (int mu = 0; mu < d; ++mu) {
+        phi[mu] = Phi[mu * nodes + x];
+        sphi += phi[mu];
+    }
+    f[x] = c - cc.w[0] * sphi;
+#pragma unroll
+    for (int mu = 0; mu < d; ++mu) {
+        const float a = cc.w[2 * mu + 1] * phi[mu];
+        const float b = cc.adv[mu] * c;
+        f[(2 * mu + 1) * nodes + x] = a + b;
+        f[(2 * mu + 2) * nodes + x] = a - b;
+    }
+}
+
+__global__ void wall_overwrite(CollideConsts cc, float* __restrict__ C, int64_t nodes)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nodes) return;
+    int64_t r = i;
+    bool wall = false;
+    for (int mu = 0; mu < cc.dim; ++mu) {
+        const int c = (int)(r % cc.n[mu]);
+        r /= cc.n[mu];
+        wall = wall || c == 0 || c == cc.n[mu] - 1;
+    }
+    if (wall) C[i] = cc.c_wall;
+}
+
+template <int Q>
+__global__ void moment_kernel(const float* __restrict__ f, float* __restrict__ C, int64_t nodes)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nodes) return;
+    float c = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) c += f[i * nodes + x];
+    C[x] = c;
+}
+
+__global__ void nonfinite_kernel(const float* __restrict__ C, int64_t nodes, int* flag)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nodes) return;
+    const float v = C[x];
+    if (!(v == v) || fabsf(v) == __builtin_inff()) atomicOr(flag, 1);
+}
+
+int64_t nodes_of(const CollideConsts& cc)
+{
+    int64_t m = 1;
+    for (int mu = 0; mu < cc.dim; ++mu) m *= cc.n[mu];
+    return m;
+}
+
+unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
+                                 const float* S, float* C_out, hipStream_t s)
+{
+    if (cc.dim == 2) {
+        const int nx = cc.n[0], ny = cc.n[1];
+        const int strips = (nx + kStrip - 1) / kStrip;
+        // enough wavefronts to fill the chip, long enough marches to amortise the halo rows
+        int rows = 64;
+        while (rows > 8 && (int64_t)strips * ((ny + rows - 1) / rows) < 8 * 1024) rows /= 2;
+        const int chunks = (ny + rows - 1) / rows;
+        const int waves = strips * chunks;
+        const unsigned blocks = (unsigned)((waves + 3) / 4);
+        if (S)
+            hipLaunchKernelGGL(collide_stream_2d<true>, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out,
+                               rows, strips, waves);
+        else
+            hipLaunchKernelGGL(collide_stream_2d<false>, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S,
+                               C_out, rows, strips, waves);
+        return hipGetLastError();
+    }
+    constexpr int NY = 8;
+    const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
+    const int sx = (nx + kStrip - 1) / kStrip;
+    const int sy = (ny + (NY - 2) - 1) / (NY - 2);
+    int planes = 64;
+    while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 2048) planes /= 2;
+    const int chunks = (nz + planes - 1) / planes;
+    const int64_t blocks = (int64_t)sx * sy * chunks;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (S)
+        hipLaunchKernelGGL((collide_stream_3d<NY, true>), dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out,
+                           Phi, S, C_out, planes, sx, sy);
+    else
+        hipLaunchKernelGGL((collide_stream_3d<NY, false>), dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in,
+                           f_out, Phi, S, C_out, planes, sx, sy);
+    return hipGetLastError();
+}
+
+hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f, hipStream_t s)
+{
+    const int64_t nodes = nodes_of(cc);
+    if (cc.Q == 5)
+        hipLaunchKernelGGL(equilibrium_init<5>, dim3(blocks_for(nodes, 256)), dim3(256), 0, s, cc, C, Phi, f, nodes);
+    else
+        hipLaunchKernelGGL(equilibrium_init<7>, dim3(blocks_for(nodes, 256)), dim3(256), 0, s, cc, C, Phi, f, nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t s)
+{
+    const int64_t nodes = nodes_of(cc);
+    hipLaunchKernelGGL(wall_overwrite, dim3(blocks_for(nodes, 256)), dim3(256), 0, s, cc, C, nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_moment(const CollideConsts& cc, const float* f, float* C, hipStream_t s)
+{
+    const int64_t nodes = nodes_of(cc);
+    if (cc.Q == 5)
+        hipLaunchKernelGGL(moment_kernel<5>, dim3(blocks_for(nodes, 256)), dim3(256), 0, s, f, C, nodes);
+    else
+        hipLaunchKernelGGL(moment_kernel<7>, dim3(blocks_for(nodes, 256)), dim3(256), 0, s, f, C, nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_check(const float* C, int64_t nodes, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks_for(nodes, 256)), dim3(256), 0, s, C, nodes, flag);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,45 @@
+// lbm_handle.h -- the solver handle behind lbm_fade_t (internal).
+#pragma once
+
+#include <string>
+
+#include "../../include/lbm_fade.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+struct AdjointState;
+}
+
+struct lbm_fade {
+    lbm_grid grid;
+    lbm_params params;
+    int dim = 0, Q = 0;
+    int64_t nodes = 0;
+    int device = 0;
+    float* f[2] = {nullptr, nullptr};
+    int cur = 0;  // f[cur] holds the current populations
+    float* C = nullptr;
+    float* Phi = nullptr;
+    float* S = nullptr;
+    void* opmem = nullptr;  // generators, corrections and BF16 splits of all axes
+    int* flag = nullptr;
+    lbm::AxisOp ops[3];
+    lbm::AxisLayout lays[3];
+    lbm::CollideConsts cc;
+    bool has_state = false;
+    int64_t steps_done = 0;
+    // FP64 host copies used by the adjoint
+    double lam_bar[9] = {0};  // flux-block relaxation times lambda-bar
+    double lam_inv[9] = {0};  // lambda-bar^-1 (flux block of Lambda)
+    double e2 = 0, w0 = 0, wi = 0;
+    lbm::AdjointState* adj = nullptr;
+};
+
+namespace lbm {
+// Fractional term of every axis of C into Phi (d consecutive node fields).
+int fade_run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s);
+// Adjoint driver (adjoint.hip).
+int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_device, lbm_grads* out,
+                float* dC0, float* dS, hipStream_t s, std::string& msg);
+void adjoint_free(AdjointState* a);
+}  // namespace lbm

@@ -1,0 +1,62 @@
+// lbm_internal.h -- structures shared by the host runtime (lbm_fade.hip) and
+// the kernel launchers (fractional_gemm.hip, collide_stream.hip, adjoint.hip).
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kMaxQ = 7;
+
+// Device-side description of the fractional operator along one axis
+// (Sec. 2.4): Phi[j] = sum_k T(j - k) C[k] + corr0[j] C[0] + corrN[j] C[N],
+// with T and the boundary corrections pre-multiplied by
+// g dx^gamma / Gamma(2 + gamma) and by p (lower part) / (1 - p) (upper part).
+struct AxisOp {
+    int n;               // nodes on the axis, N = n - 1
+    int lower_only;      // p == 1: T(d) = 0 for d < 0
+    int upper_only;      // p == 0: T(d) = 0 for d > 0
+    const float* gen;    // T(d) at gen[d + n - 1], d in [-(n-1), n-1]
+    const float* corr0;  // n values
+    const float* corrN;  // n values
+    const uint16_t* gen_hi;  // BF16 bits of T split hi/lo (same indexing)
+    const uint16_t* gen_lo;
+};
+
+// Strided view of a node field for the operator along one axis.
+//   contiguous axis (x): line l, node j  ->  l * n + j
+//   other axes: batch b, node j, line l  ->  b * batch_stride + j * j_stride + l
+struct AxisLayout {
+    int contiguous;        // 1 for the x axis
+    int64_t lines;         // lines per batch (contiguous axis: all lines)
+    int64_t j_stride;      // stride of the axis index (strided case)
+    int64_t batch_stride;  // strided case
+    int batches;           // strided case
+};
+
+// Constants of the fused collide-stream kernel (Sec. 2.2-2.5).
+struct CollideConsts {
+    int dim, Q;
+    int n[3];
+    float w[kMaxQ];         // lattice weights
+    float adv[3];           // (dt/dx) u_mu w / e^2: f^eq_{2mu+1} += adv C, f^eq_{2mu+2} -= adv C
+    float R[kMaxQ * kMaxQ]; // M^-1 Lambda M (BGK: I / lambda), row-major
+    float wSdt[kMaxQ];      // w_i dt (multiplies S)
+    float c_wall;
+};
+
+// Kernel launchers (host functions).  All return a hipError_t.
+hipError_t launch_fractional(const AxisOp& op, const AxisLayout& lay, int precision, const float* C, float* Phi,
+                             hipStream_t s);
+hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
+                                 const float* S, float* C_out, hipStream_t s);
+hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f,
+                                   hipStream_t s);
+hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t s);
+hipError_t launch_moment(const CollideConsts& cc, const float* f, float* C, hipStream_t s);
+hipError_t launch_nonfinite_check(const float* C, int64_t nodes, int* flag, hipStream_t s);
+bool have_bf16x3();
+
+}  // namespace lbm

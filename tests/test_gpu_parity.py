@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element
+by element on the same seeded inputs.
+
+Tolerances (FP32 path): the fractional term accumulates n products in FP32,
+so each value carries a relative error of order n * 2^-24 of
+sum_k |K_jk| |C_k| at worst (sqrt(n) * 2^-24 typical); a full time step adds
+FP32 rounding of order 2^-24 times the largest population magnitude; a run of
+steps is held to the relative L2 bound 1e-5 of the FP32 target.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _solver(cfg, precision="fp32", **kw):
+    from paper_1706_09161_amd import LbmFade
+
+    return LbmFade.from_config(cfg, precision=precision, **kw)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a, np.float64) - b).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def _banner(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+PHI_CASES = [
+    # (dim, n, alpha, p) -- several tiles plus ragged tails, one-sided and two-sided operators
+    (2, [67, 45], [1.3, 1.8], [0.3, 0.8]),
+    (2, [130, 97], [1.5, 1.2], [1.0, 0.0]),
+    (2, [64, 64], [1.5, 1.5], [0.5, 0.5]),
+    (2, [3, 5], [1.7, 1.1], [0.2, 0.9]),
+    (2, [200, 131], [1.05, 1.95], [0.0, 1.0]),
+    (3, [21, 18, 13], [1.5, 1.6, 1.8], [0.5, 0.2, 0.9]),
+    (3, [40, 33, 35], [1.2, 1.9, 1.4], [1.0, 0.0, 0.6]),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_simt"])
+@pytest.mark.parametrize("case", PHI_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
+def test_fractional_term_matches_oracle(case, precision):
+    dim, n, alpha, p = case
+    _banner(f"phi {precision} dim={dim} n={n}")
+    cfg = synth.small(dim, n, alpha=alpha, p=p, seed=31)
+    cfg["g"] = [1.3, 0.7, 1.1][:dim]
+    cfg["dx"] = 0.5
+    rng = np.random.default_rng(17)
+    C = rng.uniform(0.0, 1.0, synth.shape(cfg)).astype(np.float32)
+    ref = oracle.phi(cfg, C.astype(np.float64))
+    with _solver(cfg, precision) as s:
+        got = s.apply_phi(torch.from_numpy(C).cuda()).cpu().numpy().astype(np.float64)
+        got_host = s.apply_phi(C)
+    assert np.array_equal(got, got_host.astype(np.float64))
+    # C >= 0 and every weight >= 0, so ref is also sum_k |K||C|
+    nmax = max(n)
+    bound = 4 * nmax * 2.0**-24 * np.abs(ref) + 1e-30
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / (np.abs(ref) + 1e-30))
+    assert _rel_l2(got, ref) < 2e-6
+
+
+@pytest.mark.parametrize("dim,n,collision,with_source,c_wall", [
+    (2, [37, 29], "MRT", False, 0.0),
+    (2, [70, 66], "MRT", True, 0.25),
+    (2, [33, 40], "BGK", True, 0.0),
+    (2, [3, 3], "MRT", False, 0.5),
+    (3, [19, 14, 11], "MRT", True, 0.0),
+    (3, [9, 21, 16], "BGK", False, 0.3),
+])
+def test_one_step_matches_oracle(dim, n, collision, with_source, c_wall):
+    """One full step from the same population state (set_f), every population of every node."""
+    _banner(f"one-step dim={dim} n={n} {collision} src={with_source}")
+    cfg = synth.small(dim, n, seed=41, collision=collision, with_source=with_source, c_wall=c_wall)
+    S = synth.source(cfg)
+    f0 = oracle.init(cfg, synth.initial_C(cfg))
+    f0 = oracle.step(cfg, f0, 3, S=S)
+    f32 = f0.astype(np.float32)
+    ref = oracle.step(cfg, f32.astype(np.float64), 1, S=None if S is None else S.astype(np.float32).astype(np.float64))
+    with _solver(cfg) as s:
+        s.set_f(torch.from_numpy(f32).cuda())
+        if S is not None:
+            s.set_source(S.astype(np.float32))
+        s.step(1)
+        got = s.get_f(device=False).astype(np.float64)
+        C = s.get_C(device=False).astype(np.float64)
+    scale = np.abs(f0).max()
+    assert np.abs(got - ref).max() <= 2e-6 * scale
+    assert np.abs(C - ref.sum(axis=0)).max() <= 2e-6 * scale
+
+
+def test_end_to_end_small_workload_fp32():
+    """The 64 x 64 workload (200 steps, MRT): FP32 GPU vs FP64 oracle, relative L2 <= 1e-5."""
+    cfg = synth.config("c1_64sq")
+    _banner("c1 end-to-end")
+    C0 = synth.initial_C(cfg)
+    ref = oracle.run(cfg, C0.astype(np.float32).astype(np.float64), cfg["steps"])
+    with _solver(cfg) as s:
+        s.set_C(C0.astype(np.float32))
+        s.step(cfg["steps"])
+        got = s.get_C(device=False)
+    err = _rel_l2(got, ref)
+    print(f"[gpu-parity] c1 rel L2 = {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("dim,n,collision", [(2, [75, 58], "MRT"), (3, [24, 19, 21], "MRT"), (2, [41, 41], "BGK")])
+def test_end_to_end_random_problems(dim, n, collision):
+    cfg = synth.small(dim, n, seed=51, collision=collision, with_source=True, c_wall=0.1)
+    _banner(f"end-to-end dim={dim} n={n} {collision}")
+    C0 = synth.initial_C(cfg).astype(np.float32)
+    S = synth.source(cfg).astype(np.float32)
+    steps = 60
+    ref = oracle.run(cfg, C0.astype(np.float64), steps, S=S.astype(np.float64))
+    with _solver(cfg) as s:
+        s.set_C(C0)
+        s.set_source(torch.from_numpy(S).cuda())
+        s.step(steps)
+        got = s.get_C(device=False)
+    assert _rel_l2(got, ref) <= 1e-5
+
+
+def _sample_nodes(cfg, count, seed):
+    """Random nodes plus every corner and a few wall nodes."""
+    shape = synth.shape(cfg)
+    nodes = synth.nodes(cfg)
+    rng = np.random.default_rng(seed)
+    pick = set(rng.integers(0, nodes, count).tolist())
+    d = cfg["dim"]
+    n = cfg["n"][:d]
+    for corner in np.ndindex(*([2] * d)):
+        c = [0 if b == 0 else n[mu] - 1 for mu, b in enumerate(corner)]
+        idx = 0
+        mul = 1
+        for mu in range(d):
+            idx += c[mu] * mul
+            mul *= n[mu]
+        pick.add(idx)
+    for _ in range(8):  # wall nodes
+        mu = int(rng.integers(0, d))
+        c = [int(rng.integers(0, n[nu])) for nu in range(d)]
+        c[mu] = 0 if rng.random() < 0.5 else n[mu] - 1
+        idx = 0
+        mul = 1
+        for nu in range(d):
+            idx += c[nu] * mul
+            mul *= n[nu]
+        pick.add(idx)
+    return np.array(sorted(pick), dtype=np.int64)
+
+
+@pytest.mark.parametrize("name,precision", [("c2_1024sq", "fp32"), ("c5_512sq_hidden", "fp32")])
+def test_full_size_sampled_step(name, precision):
+    """At the benchmark's full size and launch configuration: after some GPU
+    steps, one more GPU step is compared at sampled nodes with the oracle's
+    step from the same populations."""
+    cfg = synth.config(name)
+    _banner(f"sampled full-size {name} {precision}")
+    with _solver(cfg, precision) as s:
+        s.set_C(synth.initial_C(cfg).astype(np.float32))
+        s.step(20)
+        f = s.get_f(device=False).astype(np.float64)
+        s.step(1)
+        f1 = s.get_f(device=False).reshape(2 * cfg["dim"] + 1, -1)
+    nodes = _sample_nodes(cfg, 300, 7)
+    ref = oracle.step_sampled(cfg, f, nodes)
+    got = f1[:, nodes].astype(np.float64)
+    scale = np.abs(f).max()
+    err = np.abs(got - ref).max() / scale
+    print(f"[gpu-parity] {name} sampled max err / max|f| = {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_error_codes_on_device():
+    from paper_1706_09161_amd import LbmError, _lib
+
+    cfg = synth.small(2, [16, 16], seed=3)
+    with _solver(cfg, nonfinite_check_every=1) as s:
+        with pytest.raises(LbmError) as ei:
+            s.step(1)
+        assert ei.value.code == _lib.LBM_ESTATE
+        C0 = np.ones((16, 16), np.float32)
+        C0[5, 5] = np.nan
+        s.set_C(C0)
+        with pytest.raises(LbmError) as ei:
+            s.step(3)
+        assert ei.value.code == _lib.LBM_ENONFINITE
+        with pytest.raises(ValueError):
+            s.set_C(np.ones(10, np.float32))
+
+
+def test_zero_steps_and_repeat_calls_are_consistent():
+    cfg = synth.small(2, [50, 34], seed=8)
+    C0 = synth.initial_C(cfg).astype(np.float32)
+    with _solver(cfg) as s:
+        s.set_C(C0)
+        s.step(0)
+        a = s.get_C(device=False)
+        s.step(5)
+        s.step(5)
+        b = s.get_C(device=False)
+        s.set_C(C0)
+        s.step(10)
+        c = s.get_C(device=False)
+    ref0 = oracle.moment(cfg, oracle.init(cfg, C0.astype(np.float64)))
+    assert np.abs(a - ref0).max() < 1e-5
+    assert np.array_equal(b, c)  # deterministic
