@@ -7,7 +7,7 @@ and the benchmark's CPU-baseline leg import this package; the GPU library never
 does.  It shares no code with the GPU path: both sides read their inputs from
 ``synth`` (seeded generators that hold none of the method's arithmetic).
 
-``oracle.adjoint`` adds the hand-written FP64 adjoint of the same step.
+``adjoint`` is the hand-written FP64 adjoint (vector-Jacobian product) of n steps.
 """
 from __future__ import annotations
 
@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfade_oracle.so")
-_SOURCES = ["fade_oracle.c", "fade_oracle_adjoint.c"]
+_SOURCES = ["fade_oracle.c"]
 
 
 def build(force: bool = True) -> str:
@@ -83,9 +83,7 @@ def lib():
             "fo_step_sampled": (ctypes.c_int, [P, dp, dp, ip, ctypes.c_int64, dp]),
             "fo_threads": (ctypes.c_int, []),
         }
-        if hasattr(L, "fo_adjoint"):
-            sig["fo_adjoint"] = (ctypes.c_int, [P, dp, dp, ctypes.c_int64, dp, dp, dp, dp, dp, dp])
-            sig["fo_step_linear"] = (ctypes.c_int, [P, dp, dp, ctypes.c_int64])
+        sig["fo_adjoint"] = (ctypes.c_int, [P, dp, dp, ctypes.c_int64, dp, dp, dp, dp, dp, dp])
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
             fn.restype = res
@@ -262,3 +260,29 @@ def run(cfg: dict, C0: np.ndarray, nsteps: int, S: np.ndarray | None = None) -> 
     f = init(cfg, C0)
     f = step(cfg, f, nsteps, S)
     return moment(cfg, f)
+
+
+def adjoint(cfg: dict, C0: np.ndarray, nsteps: int, gC: np.ndarray, S: np.ndarray | None = None):
+    """Gradients of L = <gC, C_n> (FP64): dict with dC0, dS (fields), D (d x d, symmetrised), u, p."""
+    P = make_problem(cfg)
+    shp = shape_of(cfg)
+    d = int(cfg["dim"])
+    C0 = np.ascontiguousarray(C0, dtype=np.float64).reshape(shp)
+    gC = np.ascontiguousarray(gC, dtype=np.float64).reshape(shp)
+    Sp = None
+    if S is not None:
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(shp)
+        Sp = _dp(S)
+    dC0 = np.zeros(shp)
+    dS = np.zeros(shp)
+    dD = np.zeros(9)
+    du = np.zeros(3)
+    dpv = np.zeros(3)
+    _check(lib().fo_adjoint(ctypes.byref(P), _dp(C0), Sp, int(nsteps), _dp(gC), _dp(dC0), _dp(dS), _dp(dD), _dp(du),
+                            _dp(dpv)), "adjoint")
+    return {"dC0": dC0, "dS": dS, "D": dD[: d * d].reshape(d, d), "u": du[:d], "p": dpv[:d]}
+
+
+def loss(cfg: dict, C0: np.ndarray, nsteps: int, gC: np.ndarray, S: np.ndarray | None = None) -> float:
+    """L = <gC, C_n> by the forward oracle."""
+    return float(np.sum(np.asarray(gC, np.float64) * run(cfg, C0, nsteps, S=S)))

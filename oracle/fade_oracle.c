@@ -747,3 +747,314 @@ int fo_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Adjoint (vector-Jacobian product) of n time steps, FP64.  The paper has no
+ * adjoint; this is the literal reverse of every sub-step above, in reverse
+ * order, with every forward state stored (no checkpointing).  For
+ * L = <gC, C_n>, C_n = <1|f^n>, f^0 = f^eq(C0', Phi(C0')) (C0' = C0 with the
+ * wall nodes set to c_wall) it returns dL/dC0 (zero on wall nodes), dL/dS
+ * (constant source), dL/dD (symmetrised: dL = sum_ab dD_ab deltaD_ab for a
+ * symmetric perturbation; BGK: (dL/dD0 / d) Id), dL/du and dL/dp. */
+
+/* Fractional-term data of one axis for the adjoint: coefficient tables and scalars. */
+typedef struct {
+    coeff_table T;
+    double pref, p, g;
+    int64_t len, s;
+} axis_data;
+
+static int axis_prepare(const fo_problem* P, int mu, axis_data* A)
+{
+    A->len = P->n[mu];
+    A->s = stride_of(P, mu);
+    const double gamma = 2.0 - P->alpha[mu];
+    A->pref = pow(P->dx, gamma) / tgamma(2.0 + gamma);
+    A->p = P->p[mu];
+    A->g = P->g[mu];
+    return make_table(A->len - 1, gamma, &A->T);
+}
+
+/* Adjoint of Phi_mu = K_mu C along every line of axis mu: Cbar += K^T Phibar,
+ * and dL/dp_mu += <Phibar, pref g (W+ C - W- C)>. */
+static int phi_adjoint_axis(const fo_problem* P, const axis_data* A, int mu, const double* C, const double* Phibar,
+                            double* Cbar, double* pbar)
+{
+    const int64_t nodes = nodes_of(P), len = A->len, N = len - 1, s = A->s, lines = nodes / len;
+    const int64_t m = N + 1;
+    double acc_p = 0.0;
+    int failed = 0;
+#pragma omp parallel reduction(+ : acc_p)
+    {
+        double* c = (double*)malloc(sizeof(double) * len);
+        double* pb = (double*)malloc(sizeof(double) * len);
+        double* cb = (double*)malloc(sizeof(double) * len);
+        if (!c || !pb || !cb) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t q = 0; q < lines; ++q) {
+                const int64_t base = (q % s) + (q / s) * s * len;
+                for (int64_t l = 0; l < len; ++l) {
+                    c[l] = C[base + l * s];
+                    pb[l] = Phibar[(int64_t)mu * nodes + base + l * s];
+                    cb[l] = 0.0;
+                }
+                double line_p = 0.0;
+                for (int64_t n = 0; n < len; ++n) {
+                    double splus = 0.0, sminus = 0.0;
+                    for (int64_t l = 0; l <= n; ++l) {
+                        cb[l] += pb[n] * A->pref * A->p * A->T.cp[n * m + l] * A->g;
+                        splus += A->T.cp[n * m + l] * (A->g * c[l]);
+                    }
+                    for (int64_t l = n; l <= N; ++l) {
+                        cb[l] += pb[n] * A->pref * (1.0 - A->p) * A->T.cm[n * m + l] * A->g;
+                        sminus += A->T.cm[n * m + l] * (A->g * c[l]);
+                    }
+                    line_p += pb[n] * A->pref * (splus - sminus);
+                }
+                acc_p += line_p;
+                for (int64_t l = 0; l < len; ++l) Cbar[base + l * s] += cb[l];
+            }
+        }
+        free(c);
+        free(pb);
+        free(cb);
+    }
+    if (failed) return FO_ENOMEM;
+    *pbar += acc_p;
+    return FO_OK;
+}
+
+/* Adjoint of the equilibrium at one node: given febar, adds to *Cbar, phibar[mu]
+ * and ubar[nu]. */
+static void equilibrium_adjoint(const fo_problem* P, const fo_lattice_t* L, double C, const double* febar,
+                                double* Cbar, double* phibar, double* ubar)
+{
+    *Cbar += febar[0];
+    for (int mu = 0; mu < P->dim; ++mu) phibar[mu] += -L->w[0] * febar[0];
+    for (int i = 1; i < L->Q; ++i) {
+        const int mu = (i - 1) / 2;
+        phibar[mu] += L->w[i] * febar[i];
+        double adv = 0.0;
+        for (int nu = 0; nu < P->dim; ++nu) {
+            adv += P->u[nu] * L->e[i][nu] * L->w[i];
+            ubar[nu] += febar[i] * (C / L->e2) * (P->dt / P->dx) * L->e[i][nu] * L->w[i];
+        }
+        *Cbar += febar[i] * (1.0 / L->e2) * (P->dt / P->dx) * adv;
+    }
+}
+
+int fo_adjoint(const fo_problem* P, const double* C0, const double* S, int64_t nsteps, const double* gC,
+               double* dC0, double* dS, double* dD, double* du, double* dp)
+{
+    fo_lattice_t L;
+    fo_collision K;
+    int rc = make_collision(P, &K);
+    if (rc) return rc;
+    if (nsteps < 0) return FO_EINVAL;
+    lattice_of(P->dim, &L);
+    const int Q = L.Q, d = P->dim;
+    const int64_t nodes = nodes_of(P);
+    double* fs = (double*)malloc(sizeof(double) * Q * nodes * (nsteps + 1)); /* f^0 .. f^n */
+    double* C = (double*)malloc(sizeof(double) * nodes);
+    double* Phi = (double*)malloc(sizeof(double) * nodes * d);
+    double* fbar = (double*)malloc(sizeof(double) * Q * nodes);
+    double* fsbar = (double*)malloc(sizeof(double) * Q * nodes);
+    double* Cbar = (double*)malloc(sizeof(double) * nodes);
+    double* Phibar = (double*)malloc(sizeof(double) * nodes * d);
+    axis_data AX[3];
+    int nax = 0;
+    double Lambar[49] = {0}, lambar_bgk = 0.0, ubar[3] = {0, 0, 0}, pbar[3] = {0, 0, 0};
+    if (!fs || !C || !Phi || !fbar || !fsbar || !Cbar || !Phibar) {
+        rc = FO_ENOMEM;
+        goto done;
+    }
+    for (nax = 0; nax < d; ++nax)
+        if (axis_prepare(P, nax, &AX[nax])) {
+            rc = FO_ENOMEM;
+            goto done;
+        }
+    /* forward, storing every state */
+    rc = fo_init(P, C0, fs);
+    for (int64_t t = 0; t < nsteps && !rc; ++t) {
+        memcpy(fs + (t + 1) * Q * nodes, fs + t * Q * nodes, sizeof(double) * Q * nodes);
+        rc = fo_step(P, fs + (t + 1) * Q * nodes, S, 1);
+    }
+    if (rc) goto done;
+    /* L = <gC, sum_i f^n_i> */
+    for (int64_t x = 0; x < nodes; ++x)
+        for (int i = 0; i < Q; ++i) fbar[(int64_t)i * nodes + x] = gC[x];
+    for (int64_t x = 0; x < nodes; ++x) dS[x] = 0.0;
+
+    for (int64_t t = nsteps - 1; t >= 0; --t) {
+        const double* f = fs + t * Q * nodes;
+        /* reverse of the Dirichlet rule and the streaming: fbar -> fsbar */
+        memset(fsbar, 0, sizeof(double) * Q * nodes);
+        for (int64_t y = 0; y < nodes; ++y) {
+            int64_t c[3];
+            coords_of(P, y, c);
+            int unknown[7] = {0}, nu = 0;
+            int64_t src[7];
+            for (int i = 0; i < Q; ++i) {
+                int inside = 1;
+                int64_t s_idx = 0, mul = 1;
+                for (int mu = 0; mu < d; ++mu) {
+                    const int64_t sc = c[mu] - L.e[i][mu];
+                    if (sc < 0 || sc >= P->n[mu]) inside = 0;
+                    s_idx += sc * mul;
+                    mul *= P->n[mu];
+                }
+                src[i] = s_idx;
+                if (!inside) {
+                    unknown[i] = 1;
+                    ++nu;
+                }
+            }
+            double avg = 0.0;
+            if (nu > 0) {
+                for (int i = 0; i < Q; ++i)
+                    if (unknown[i]) avg += fbar[(int64_t)i * nodes + y];
+                avg /= (double)nu;
+            }
+            for (int i = 0; i < Q; ++i)
+                if (!unknown[i]) fsbar[(int64_t)i * nodes + src[i]] += fbar[(int64_t)i * nodes + y] - avg;
+        }
+        /* reverse of the collision and the equilibrium at every node */
+        fo_moment(P, f, C);
+        rc = fo_phi(P, C, Phi);
+        if (rc) goto done;
+        memset(Phibar, 0, sizeof(double) * nodes * d);
+        double lam_acc[49] = {0}, lb_acc = 0.0, u_acc[3] = {0, 0, 0};
+        for (int64_t x = 0; x < nodes; ++x) {
+            double fx[7], phi[3], feq[7], fb[7], feqbar[7], phib[3] = {0, 0, 0}, cb = 0.0;
+            for (int i = 0; i < Q; ++i) {
+                fx[i] = f[(int64_t)i * nodes + x];
+                fb[i] = fsbar[(int64_t)i * nodes + x];
+            }
+            for (int mu = 0; mu < d; ++mu) phi[mu] = Phi[(int64_t)mu * nodes + x];
+            equilibrium(P, &L, C[x], phi, feq);
+            double sb = 0.0;
+            for (int i = 0; i < Q; ++i) sb += L.w[i] * P->dt * fb[i];
+            dS[x] += sb;
+            double fdir[7];
+            if (K.collision == 0) {
+                const double r = 1.0 / K.lambda_bgk;
+                for (int i = 0; i < Q; ++i) {
+                    fdir[i] = (1.0 - r) * fb[i];
+                    feqbar[i] = r * fb[i];
+                    lb_acc += fb[i] * (fx[i] - feq[i]) / (K.lambda_bgk * K.lambda_bgk);
+                }
+            } else {
+                double dev[7], m[7], lmbar[7], mbar[7], devbar[7];
+                for (int i = 0; i < Q; ++i) dev[i] = fx[i] - feq[i];
+                for (int r = 0; r < Q; ++r) {
+                    double s = 0.0;
+                    for (int cc = 0; cc < Q; ++cc) s += K.M[r * Q + cc] * dev[cc];
+                    m[r] = s;
+                }
+                for (int r = 0; r < Q; ++r) { /* lmbar = -Minv^T fb */
+                    double s = 0.0;
+                    for (int cc = 0; cc < Q; ++cc) s += K.Minv[cc * Q + r] * fb[cc];
+                    lmbar[r] = -s;
+                }
+                for (int r = 0; r < Q; ++r)
+                    for (int cc = 0; cc < Q; ++cc) lam_acc[r * Q + cc] += lmbar[r] * m[cc];
+                for (int r = 0; r < Q; ++r) { /* mbar = Lam^T lmbar */
+                    double s = 0.0;
+                    for (int cc = 0; cc < Q; ++cc) s += K.Lam[cc * Q + r] * lmbar[cc];
+                    mbar[r] = s;
+                }
+                for (int r = 0; r < Q; ++r) { /* devbar = M^T mbar */
+                    double s = 0.0;
+                    for (int cc = 0; cc < Q; ++cc) s += K.M[cc * Q + r] * mbar[cc];
+                    devbar[r] = s;
+                }
+                for (int i = 0; i < Q; ++i) {
+                    fdir[i] = fb[i] + devbar[i];
+                    feqbar[i] = -devbar[i];
+                }
+            }
+            equilibrium_adjoint(P, &L, C[x], feqbar, &cb, phib, u_acc);
+            for (int mu = 0; mu < d; ++mu) Phibar[(int64_t)mu * nodes + x] = phib[mu];
+            Cbar[x] = cb;
+            for (int i = 0; i < Q; ++i) fbar[(int64_t)i * nodes + x] = fdir[i];
+        }
+        for (int k = 0; k < Q * Q; ++k) Lambar[k] += lam_acc[k];
+        lambar_bgk += lb_acc;
+        for (int mu = 0; mu < d; ++mu) ubar[mu] += u_acc[mu];
+        /* reverse of the fractional term, then of the moment */
+        for (int mu = 0; mu < d; ++mu) {
+            rc = phi_adjoint_axis(P, &AX[mu], mu, C, Phibar, Cbar, &pbar[mu]);
+            if (rc) goto done;
+        }
+        for (int64_t x = 0; x < nodes; ++x)
+            for (int i = 0; i < Q; ++i) fbar[(int64_t)i * nodes + x] += Cbar[x];
+    }
+    /* reverse of the initial state f^0 = f^eq(C0', Phi(C0')) */
+    for (int64_t x = 0; x < nodes; ++x) {
+        int64_t c[3];
+        coords_of(P, x, c);
+        C[x] = on_wall(P, c) ? P->c_wall : C0[x];
+    }
+    rc = fo_phi(P, C, Phi);
+    if (rc) goto done;
+    for (int64_t x = 0; x < nodes; ++x) {
+        double feqbar[7], phib[3] = {0, 0, 0}, cb = 0.0;
+        for (int i = 0; i < Q; ++i) feqbar[i] = fbar[(int64_t)i * nodes + x];
+        equilibrium_adjoint(P, &L, C[x], feqbar, &cb, phib, ubar);
+        for (int mu = 0; mu < d; ++mu) Phibar[(int64_t)mu * nodes + x] = phib[mu];
+        Cbar[x] = cb;
+    }
+    for (int mu = 0; mu < d; ++mu) {
+        rc = phi_adjoint_axis(P, &AX[mu], mu, C, Phibar, Cbar, &pbar[mu]);
+        if (rc) goto done;
+    }
+    for (int64_t x = 0; x < nodes; ++x) {
+        int64_t c[3];
+        coords_of(P, x, c);
+        dC0[x] = on_wall(P, c) ? 0.0 : Cbar[x];
+    }
+    /* relaxation gradients -> D */
+    {
+        const double scale = P->dt / (L.e2 * P->dx * P->dx);
+        double G[9] = {0};
+        if (K.collision == 0) {
+            for (int a = 0; a < d; ++a) G[a * d + a] = lambar_bgk * scale / d;
+        } else {
+            /* Lambda = (Lambda^-1)^-1: d(Lambda^-1) bar = -Lambda^T Lambar Lambda^T */
+            double T1[49], T2[49];
+            for (int r = 0; r < Q; ++r)
+                for (int cc = 0; cc < Q; ++cc) {
+                    double s = 0.0;
+                    for (int k = 0; k < Q; ++k) s += K.Lam[k * Q + r] * Lambar[k * Q + cc];
+                    T1[r * Q + cc] = s;
+                }
+            for (int r = 0; r < Q; ++r)
+                for (int cc = 0; cc < Q; ++cc) {
+                    double s = 0.0;
+                    for (int k = 0; k < Q; ++k) s += T1[r * Q + k] * K.Lam[cc * Q + k];
+                    T2[r * Q + cc] = -s;
+                }
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) G[a * d + b] = T2[(1 + a) * Q + (1 + b)] * scale;
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) dD[a * d + b] = 0.5 * (G[a * d + b] + G[b * d + a]);
+    }
+    for (int mu = 0; mu < d; ++mu) {
+        du[mu] = ubar[mu];
+        dp[mu] = pbar[mu];
+    }
+done:
+    for (int k = 0; k < nax; ++k) free_table(&AX[k].T);
+    free(fs);
+    free(C);
+    free(Phi);
+    free(fbar);
+    free(fsbar);
+    free(Cbar);
+    free(Phibar);
+    return rc;
+}

@@ -1,9 +1,9 @@
 """Write oracle reference results used by the GPU tests and the benchmark.
 
 Calls only ``oracle`` and ``synth``: every stored value is the FP64 oracle's.
-For a workload of n x n nodes the final concentration is stored on the
-sub-grid of every 4th node in x and y (index [::4, ::4]), in FP64, together
-with the workload name and step count.
+The final concentration is stored on the sub-grid of every 4th node per
+axis in 2D (every 8th in 3D), in FP64, together with the workload name,
+step count and the L2 norm of the full field.
 
     python tests/golden/make_reference.py c2_1024sq
 """
@@ -19,11 +19,13 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-STRIDE = 4
+def stride_of(dim: int) -> int:
+    return 4 if dim == 2 else 8
 
 
 def reference_path(name: str, steps: int) -> str:
-    return os.path.join(HERE, f"ref_{name}_{steps}steps_every{STRIDE}.npz")
+    cfg = synth.config(name)
+    return os.path.join(HERE, f"ref_{name}_{steps}steps_every{stride_of(cfg['dim'])}.npz")
 
 
 def make(name: str, steps: int | None = None) -> str:
@@ -36,9 +38,10 @@ def make(name: str, steps: int | None = None) -> str:
     t = time.time()
     C = oracle.run(cfg, C0, steps, S=S)
     dt = time.time() - t
-    sl = (slice(None, None, STRIDE),) * cfg["dim"]
+    stride = stride_of(cfg["dim"])
+    sl = (slice(None, None, stride),) * cfg["dim"]
     path = reference_path(name, steps)
-    np.savez(path, C=C[sl], name=name, steps=steps, stride=STRIDE, full_l2=np.linalg.norm(C.ravel()),
+    np.savez(path, C=C[sl], name=name, steps=steps, stride=stride, full_l2=np.linalg.norm(C.ravel()),
              seconds=dt, threads=oracle.threads())
     print(f"{name}: {steps} steps in {dt:.1f} s on {oracle.threads()} threads -> {path}")
     return path
