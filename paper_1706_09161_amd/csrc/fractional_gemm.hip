@@ -18,6 +18,7 @@
 // In both cases the MFMA's lane-varying output index is the memory-contiguous
 // one, so stores are coalesced.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
 #include "lbm_internal.h"
 
@@ -68,68 +69,56 @@ __global__ __launch_bounds__(256) void fractional_simt(AxisOp op, AxisLayout lay
 }
 
 // ---------------------------------------------------------------------------
-// Tile bookkeeping shared by the MFMA kernels.
-struct TileCoord {
-    int m0, n0;  // first row / column of the output tile (GEMM coordinates)
-    int batch;
-};
-
-// Map the linear workgroup id to a tile.  Consecutive workgroup ids go to
-// different XCDs (round robin over 8); remap so that every XCD owns a
-// contiguous range of tiles, and order tiles so that those sharing a panel of
-// C (the large operand) are adjacent: they then hit the same L2.
-__device__ inline TileCoord tile_of(int tiles_toep, int tiles_c, bool toep_is_m, int total)
-{
-    int bid = blockIdx.x;
-    int lin = bid;
-    if ((total & 7) == 0) lin = (bid & 7) * (total >> 3) + (bid >> 3);
-    const int tt = lin % tiles_toep;
-    const int rest = lin / tiles_toep;
-    const int tc = rest % tiles_c;
-    TileCoord r;
-    r.batch = rest / tiles_c;
-    if (toep_is_m) {
-        r.m0 = tt;
-        r.n0 = tc;
-    } else {
-        r.m0 = tc;
-        r.n0 = tt;
-    }
-    return r;
-}
-
-// ---------------------------------------------------------------------------
-// FP32 MFMA kernel, v_mfma_f32_32x32x2_f32.  Workgroup tile BM x BN, 4 waves
-// in a 2 x 2 arrangement, each wave (BM/2) x (BN/2) in 32 x 32 blocks.
+// FP32 MFMA kernel, v_mfma_f32_32x32x2_f32.
+//
 // Operand convention for 32x32x2: lane l supplies A(i = l%32, kk = l/32) and
 // B(kk = l/32, j = l%32); accumulator register r of lane l holds
 // D(8*(r/4) + 4*(l/32) + r%4, l%32).
-template <bool CONTIG, int BM, int BN, int BK, int VEC>
-__global__ __launch_bounds__(kThreads) void fractional_f32_mfma(AxisOp op, AxisLayout lay,
-                                                                 const float* __restrict__ C,
-                                                                 float* __restrict__ Phi, int tiles_m, int tiles_n,
-                                                                 int total)
+//
+// Workgroup tile BM x BN, 4 wavefronts arranged WAVES_M x WAVES_N x KSPLIT.
+// Every wavefront owns a 64 x 64 output tile (2 x 2 blocks of 32 x 32, four
+// independent accumulator chains); with KSPLIT > 1 the wavefronts of a
+// workgroup split each k chunk between them and their partial tiles are
+// summed through LDS at the end.  Small grids use 64 x 64 x (split-K 4) to
+// keep enough workgroups for 256 CUs; large grids use 128 x 128.
+//
+// All axes of one time step go in one launch: workgroup ids are split into
+// per-axis ranges, axis 0 (the contiguous x axis) first.
+
+
+template <bool CONTIG, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int KSPLIT, int VEC>
+__device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayout& lay, const float* __restrict__ C,
+                                                float* __restrict__ Phi, int tiles_m, int tiles_n, int bid, int total,
+                                                float* smem)
 {
-    constexpr int WM = BM / 2, WN = BN / 2;
-    constexpr int MB = WM / 32, NB = WN / 32;
-    // C tile in LDS.  Strided: [BK][BN + PADS] (row k, column = line).
-    // Contiguous: [BM][BK + PADC] (row = line, column k).
+    static_assert(WAVES_M * WAVES_N * KSPLIT == kWaves, "4 wavefronts per workgroup");
+    static_assert(BM == WAVES_M * 64 && BN == WAVES_N * 64, "64 x 64 per wavefront");
+    static_assert(BK % (2 * KSPLIT) == 0, "k chunk");
+    constexpr int MB = 2, NB = 2;
+    constexpr int KW = BK / KSPLIT;  // k values per wavefront and chunk
     constexpr int PADS = 4, PADC = 1;
     constexpr int TILE = CONTIG ? BM * (BK + PADC) : BK * (BN + PADS);
-    extern __shared__ float smem[];
     float* tile0 = smem;
     float* tile1 = smem + TILE;
     float* gl = smem + 2 * TILE;  // generator window
 
     const int n = op.n, N = n - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wk = wave % KSPLIT;
+    const int wmn = wave / KSPLIT;
+    const int wm = wmn / WAVES_N, wn = wmn % WAVES_N;
 
-    // Toeplitz index runs over rows (strided) or columns (contiguous).
+    // tile of this workgroup; the Toeplitz index runs over rows (strided) or
+    // columns (contiguous); consecutive ids on one XCD share a panel of C
     const int tiles_toep = CONTIG ? tiles_n : tiles_m;
     const int tiles_c = CONTIG ? tiles_m : tiles_n;
-    TileCoord tc = tile_of(tiles_toep, tiles_c, !CONTIG, total);
-    const int m0 = tc.m0 * BM, n0 = tc.n0 * BN;
+    int lin = bid;
+    if ((total & 7) == 0) lin = (bid & 7) * (total >> 3) + (bid >> 3);
+    const int tt = lin % tiles_toep;
+    const int rest = lin / tiles_toep;
+    const int tcid = rest % tiles_c;
+    const int batch = rest / tiles_c;
+    const int m0 = (CONTIG ? tcid : tt) * BM, n0 = (CONTIG ? tt : tcid) * BN;
     const int R0 = CONTIG ? n0 : m0;
     constexpr int RB = CONTIG ? BN : BM;
 
@@ -152,8 +141,8 @@ __global__ __launch_bounds__(kThreads) void fractional_f32_mfma(AxisOp op, AxisL
     const float* Cb = C;
     float* Pb = Phi;
     if (!CONTIG) {
-        Cb += (int64_t)tc.batch * lay.batch_stride;
-        Pb += (int64_t)tc.batch * lay.batch_stride;
+        Cb += (int64_t)batch * lay.batch_stride;
+        Pb += (int64_t)batch * lay.batch_stride;
     }
     const int64_t js = lay.j_stride;
 
@@ -232,31 +221,31 @@ __global__ __launch_bounds__(kThreads) void fractional_f32_mfma(AxisOp op, AxisL
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     const int li = lane & 31, lk = lane >> 5;
-    if (nk > 0) {
-        load_tile(kb);
-        store_tile(tile0);
-    }
+    const int rowA = (CONTIG ? 0 : m0) + wm * 64;  // first Toeplitz row / C-tile row of this wavefront
+    const int colB = (CONTIG ? n0 : 0) + wn * 64;
+    load_tile(kb);
+    store_tile(tile0);
     __syncthreads();
 
     for (int t = 0; t < nk; ++t) {
         const int k0 = kb + t * BK;
-        float* cur = (t & 1) ? tile1 : tile0;
+        const float* cur = (t & 1) ? tile1 : tile0;
         float* nxt = (t & 1) ? tile0 : tile1;
         if (t + 1 < nk) load_tile(k0 + BK);
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 2) {
+        for (int kk = wk * KW; kk < wk * KW + KW; kk += 2) {
             float a[MB], b[NB];
             const int k = k0 + kk + lk;  // global k of this lane's operand element
             if constexpr (CONTIG) {
 #pragma unroll
-                for (int i = 0; i < MB; ++i) a[i] = cur[(wm * WM + i * 32 + li) * (BK + PADC) + kk + lk];
+                for (int i = 0; i < MB; ++i) a[i] = cur[(rowA + i * 32 + li) * (BK + PADC) + kk + lk];
 #pragma unroll
-                for (int j = 0; j < NB; ++j) b[j] = gl[(n0 + wn * WN + j * 32 + li) - k - dmin];
+                for (int j = 0; j < NB; ++j) b[j] = gl[(colB + j * 32 + li) - k - dmin];
             } else {
 #pragma unroll
-                for (int i = 0; i < MB; ++i) a[i] = gl[(m0 + wm * WM + i * 32 + li) - k - dmin];
+                for (int i = 0; i < MB; ++i) a[i] = gl[(rowA + i * 32 + li) - k - dmin];
 #pragma unroll
-                for (int j = 0; j < NB; ++j) b[j] = cur[(kk + lk) * (BN + PADS) + wn * WN + j * 32 + li];
+                for (int j = 0; j < NB; ++j) b[j] = cur[(kk + lk) * (BN + PADS) + colB + j * 32 + li];
             }
 #pragma unroll
             for (int i = 0; i < MB; ++i)
@@ -268,15 +257,48 @@ __global__ __launch_bounds__(kThreads) void fractional_f32_mfma(AxisOp op, AxisL
         __syncthreads();
     }
 
+    // ---- split-K reduction: every wavefront parks its partial tile in LDS
+    // (the C tiles are dead after the last barrier); the wavefronts of one
+    // output tile then each finish one of its four 32 x 32 blocks.
+    int blk_lo = 0, blk_hi = MB * NB;
+    if constexpr (KSPLIT > 1) {
+        float* red = smem;  // [KSPLIT * WAVES_M * WAVES_N][MB*NB][16][64]
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) red[((wave * MB * NB + i * NB + j) * 16 + r) * 64 + lane] = acc[i][j][r];
+        __syncthreads();
+        // wavefront wk of this output tile sums block(s) [wk * 4 / KSPLIT, (wk+1) * 4 / KSPLIT)
+        blk_lo = wk * (MB * NB) / KSPLIT;
+        blk_hi = (wk + 1) * (MB * NB) / KSPLIT;
+#pragma unroll
+        for (int bi = 0; bi < MB * NB; ++bi) {
+            if (bi < blk_lo || bi >= blk_hi) continue;
+            const int i = bi / NB, j = bi % NB;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float v = 0.f;
+#pragma unroll
+                for (int s = 0; s < KSPLIT; ++s)
+                    v += red[(((wmn * KSPLIT + s) * MB * NB + bi) * 16 + r) * 64 + lane];
+                acc[i][j][r] = v;
+            }
+        }
+    }
+
     // ---- epilogue: boundary columns and store
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
+        for (int j = 0; j < NB; ++j) {
+            const int bi = i * NB + j;
+            if (bi < blk_lo || bi >= blk_hi) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int mm = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
-                const int nn = n0 + wn * WN + j * 32 + li;
+                const int mm = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+                const int nn = n0 + wn * 64 + j * 32 + li;
                 if constexpr (CONTIG) {
                     const int64_t line = mm;
                     const int jj = nn;
@@ -298,61 +320,122 @@ __global__ __launch_bounds__(kThreads) void fractional_f32_mfma(AxisOp op, AxisL
                     }
                 }
             }
+        }
 }
 
-template <bool CONTIG, int BM, int BN, int BK, int VEC>
-hipError_t run_f32(const AxisOp& op, const AxisLayout& lay, const float* C, float* Phi, hipStream_t s)
+template <int BM, int BN, int BK, int WAVES_M, int WAVES_N, int KSPLIT, int VEC_X, int VEC_S>
+__global__ __launch_bounds__(kThreads) void fractional_f32_mfma(FracLaunch L)
 {
-    const int n = op.n;
-    int tiles_m, tiles_n, batches;
-    if (CONTIG) {
-        tiles_m = (int)((lay.lines + BM - 1) / BM);
-        tiles_n = (n + BN - 1) / BN;
-        batches = 1;
-    } else {
-        tiles_m = (n + BM - 1) / BM;
-        tiles_n = (int)((lay.lines + BN - 1) / BN);
-        batches = lay.batches;
+    extern __shared__ float smem[];
+    const int bid = blockIdx.x;
+    int axis = 0;
+    while (axis + 1 < L.naxes && bid >= L.first[axis + 1]) ++axis;  // uniform per workgroup
+    const int local = bid - L.first[axis];
+    const int total = L.first[axis + 1] - L.first[axis];
+    if (axis == 0)
+        fractional_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C, L.Phi[0],
+                                                                          L.tiles_m[0], L.tiles_n[0], local, total,
+                                                                          smem);
+    else
+        fractional_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_S>(L.op[axis], L.lay[axis], L.C,
+                                                                           L.Phi[axis], L.tiles_m[axis],
+                                                                           L.tiles_n[axis], local, total, smem);
+}
+
+template <int BM, int BN, int BK, int WAVES_M, int WAVES_N, int KSPLIT>
+hipError_t run_f32(FracLaunch& L, hipStream_t s)
+{
+    size_t lds = 0;
+    int64_t grid = 0;
+    for (int a = 0; a < L.naxes; ++a) {
+        const AxisOp& op = L.op[a];
+        const AxisLayout& lay = L.lay[a];
+        const bool contig = lay.contiguous != 0;
+        if (contig) {
+            L.tiles_m[a] = (int)((lay.lines + BM - 1) / BM);
+            L.tiles_n[a] = (op.n + BN - 1) / BN;
+        } else {
+            L.tiles_m[a] = (op.n + BM - 1) / BM;
+            L.tiles_n[a] = (int)((lay.lines + BN - 1) / BN);
+        }
+        const int64_t tiles = (int64_t)L.tiles_m[a] * L.tiles_n[a] * (contig ? 1 : lay.batches);
+        L.first[a] = (int)grid;
+        grid += tiles;
+        const int tile = contig ? BM * (BK + 1) : BK * (BN + 4);
+        const int rb = contig ? BN : BM;
+        const int kspan = ((op.n + BK - 1) / BK) * BK;
+        size_t need = sizeof(float) * (2 * tile + rb + kspan);
+        if (KSPLIT > 1) need = need > sizeof(float) * 4 * 4 * 16 * 64 ? need : sizeof(float) * 4 * 4 * 16 * 64;
+        lds = need > lds ? need : lds;
     }
-    const int64_t total64 = (int64_t)tiles_m * tiles_n * batches;
-    if (total64 > 0x7fffffff) return hipErrorInvalidValue;
-    const int total = (int)total64;
-    constexpr int TILE = CONTIG ? BM * (BK + 1) : BK * (BN + 4);
-    constexpr int RB = CONTIG ? BN : BM;
-    const int kspan = ((n + BK - 1) / BK) * BK;
-    const size_t lds = sizeof(float) * (2 * TILE + RB + kspan);
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    L.first[L.naxes] = (int)grid;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fractional_f32_mfma<CONTIG, BM, BN, BK, VEC>), dim3(total), dim3(kThreads), lds, s, op, lay,
-                       C, Phi, tiles_m, tiles_n, total);
-    return hipGetLastError();
+    const bool vx = (L.op[0].n % 4) == 0;
+    bool vs = true;
+    for (int a = 1; a < L.naxes; ++a)
+        vs = vs && (L.lay[a].lines % 4) == 0 && (L.lay[a].j_stride % 4) == 0 && (L.lay[a].batch_stride % 4) == 0;
+    auto go = [&](auto kern) -> hipError_t {
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), lds, s, L);
+        return hipGetLastError();
+    };
+    if (vx && vs) return go(fractional_f32_mfma<BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 4, 4>);
+    if (vx) return go(fractional_f32_mfma<BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 4, 1>);
+    if (vs) return go(fractional_f32_mfma<BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1, 4>);
+    return go(fractional_f32_mfma<BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1, 1>);
 }
 
 }  // namespace
 
-bool have_bf16x3() { return false; }
-
-hipError_t launch_fractional(const AxisOp& op, const AxisLayout& lay, int precision, const float* C, float* Phi,
-                             hipStream_t s)
+hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
+                             float* Phi, int64_t nodes, hipStream_t s)
 {
     if (precision == 2) {
-        const int64_t total = lay.contiguous ? lay.lines * op.n : (int64_t)lay.batches * op.n * lay.lines;
-        const int64_t blocks = (total + 255) / 256;
-        hipLaunchKernelGGL(fractional_simt, dim3((unsigned)blocks), dim3(256), 0, s, op, lay, C, Phi);
-        return hipGetLastError();
-    }
-    // FP32 MFMA (the BF16 path dispatches here too until its kernel exists)
-    if (lay.contiguous) {
-        const bool vec = (op.n % 4) == 0;
-        if (op.n <= 256 || lay.lines * op.n <= (1 << 22)) {
-            return vec ? run_f32<true, 64, 64, 32, 4>(op, lay, C, Phi, s) : run_f32<true, 64, 64, 32, 1>(op, lay, C, Phi, s);
+        for (int a = 0; a < naxes; ++a) {
+            const AxisOp& op = ops[a];
+            const AxisLayout& lay = lays[a];
+            const int64_t total = lay.contiguous ? lay.lines * op.n : (int64_t)lay.batches * op.n * lay.lines;
+            const int64_t blocks = (total + 255) / 256;
+            hipLaunchKernelGGL(fractional_simt, dim3((unsigned)blocks), dim3(256), 0, s, op, lay, C, Phi + a * nodes);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
-        return vec ? run_f32<true, 128, 128, 32, 4>(op, lay, C, Phi, s) : run_f32<true, 128, 128, 32, 1>(op, lay, C, Phi, s);
+        return hipSuccess;
     }
-    const bool vec = (lay.lines % 4) == 0 && (lay.j_stride % 4) == 0 && (lay.batch_stride % 4) == 0;
-    if (lay.lines * op.n * lay.batches <= (1 << 22)) {
-        return vec ? run_f32<false, 64, 64, 32, 4>(op, lay, C, Phi, s) : run_f32<false, 64, 64, 32, 1>(op, lay, C, Phi, s);
+    FracLaunch L;
+    memset(&L, 0, sizeof(L));
+    if (precision == 1) {
+        L.naxes = naxes;
+        L.C = C;
+        for (int a = 0; a < naxes; ++a) {
+            L.op[a] = ops[a];
+            L.lay[a] = lays[a];
+            L.Phi[a] = Phi + a * nodes;
+        }
+        return launch_fractional_bf16x3(L, s);
     }
-    return vec ? run_f32<false, 128, 128, 32, 4>(op, lay, C, Phi, s) : run_f32<false, 128, 128, 32, 1>(op, lay, C, Phi, s);
+    L.naxes = naxes;
+    L.C = C;
+    for (int a = 0; a < naxes; ++a) {
+        L.op[a] = ops[a];
+        L.lay[a] = lays[a];
+        L.Phi[a] = Phi + a * nodes;
+    }
+    // work in units of 128 x 128 output tiles: below ~2 per CU, use the small
+    // split-K tiles
+    int64_t big_tiles = 0;
+    for (int a = 0; a < naxes; ++a) {
+        const int64_t m = lays[a].contiguous ? lays[a].lines : ops[a].n;
+        const int64_t nn = lays[a].contiguous ? ops[a].n : lays[a].lines * lays[a].batches;
+        big_tiles += ((m + 127) / 128) * ((nn + 127) / 128);
+    }
+    if (big_tiles < 512) return run_f32<64, 64, 64, 1, 1, 4>(L, s);
+    return run_f32<128, 128, 32, 2, 2, 1>(L, s);
 }
 
 }  // namespace lbm

@@ -126,14 +126,39 @@ bool spd(int d, const double* D)
 
 }  // namespace
 
+namespace lbm {
+// Product-rule coefficients of Sec. 2.4 for one axis with n nodes (N = n - 1):
+//   a_0 = 1, a_k = (k+1)^{g+1} - 2 k^{g+1} + (k-1)^{g+1}       (interior of (c+) and (c-))
+//   c+_{0j} = (1+g) j^g - j^{g+1} + (j-1)^{g+1}                 (first column, j >= 1)
+//   c-_{Nj} = (1+g)(N-j)^g - (N-j)^{g+1} + (N-j-1)^{g+1}        (last column, j <= N-1)
+// and the scale s = g_mu dx^gamma / Gamma(2 + gamma).
+AxisCoeffs axis_coeffs(int n, double gamma, double g, double dx)
+{
+    const int N = n - 1;
+    const double gp1 = gamma + 1.0;
+    AxisCoeffs A;
+    A.s = g * pow(dx, gamma) / tgamma(2.0 + gamma);
+    A.a.assign(n, 0.0);
+    A.cp0.assign(n, 0.0);
+    A.cmN.assign(n, 0.0);
+    A.a[0] = 1.0;
+    for (int k = 1; k <= N; ++k)
+        A.a[k] = pow((double)(k + 1), gp1) - 2.0 * pow((double)k, gp1) + pow((double)(k - 1), gp1);
+    for (int j = 1; j <= N; ++j)
+        A.cp0[j] = (1.0 + gamma) * pow((double)j, gamma) - pow((double)j, gp1) + pow((double)(j - 1), gp1);
+    for (int j = 0; j <= N - 1; ++j) {
+        const int m = N - j;
+        A.cmN[j] = (1.0 + gamma) * pow((double)m, gamma) - pow((double)m, gp1) + pow((double)(m - 1), gp1);
+    }
+    return A;
+}
+}  // namespace lbm
+
 namespace {
 
 // ---------------------------------------------------------------------------
-// Product-rule weights (Sec. 2.4).  For one axis with n nodes (N = n - 1):
-//   a_0 = 1, a_k = (k+1)^{g+1} - 2 k^{g+1} + (k-1)^{g+1}            (interior, (c+)/(c-))
-//   c+_{0j} = (1+g) j^g - j^{g+1} + (j-1)^{g+1}                      (first column, j >= 1)
-//   c-_{Nj} = (1+g)(N-j)^g - (N-j)^{g+1} + (N-j-1)^{g+1}             (last column, j <= N-1)
-// K[j][k] = s (p c+_{kj} + (1-p) c-_{kj}), s = g_mu dx^gamma / Gamma(2 + gamma).
+// Forward operator of one axis from the product-rule coefficients:
+// K[j][k] = s (p c+_{kj} + (1-p) c-_{kj}) = T(j - k) + [k == 0] corr0[j] + [k == N] corrN[j].
 struct AxisWeights {
     std::vector<double> T;      // T(d) at d + N, d in [-N, N]
     std::vector<double> corr0;  // n
@@ -143,32 +168,21 @@ struct AxisWeights {
 AxisWeights make_axis_weights(int n, double gamma, double p, double g, double dx)
 {
     const int N = n - 1;
-    const double s = g * pow(dx, gamma) / tgamma(2.0 + gamma);
-    const double gp1 = gamma + 1.0;
-    auto a = [&](int k) -> double {
-        if (k == 0) return 1.0;
-        return pow((double)(k + 1), gp1) - 2.0 * pow((double)k, gp1) + pow((double)(k - 1), gp1);
-    };
+    const lbm::AxisCoeffs A = lbm::axis_coeffs(n, gamma, g, dx);
+    const double s = A.s;
     AxisWeights W;
     W.T.assign(2 * N + 1, 0.0);
     W.corr0.assign(n, 0.0);
     W.corrN.assign(n, 0.0);
     for (int d = -N; d <= N; ++d) {
         double v;
-        if (d > 0) v = s * p * a(d);
-        else if (d < 0) v = s * (1.0 - p) * a(-d);
+        if (d > 0) v = s * p * A.a[d];
+        else if (d < 0) v = s * (1.0 - p) * A.a[-d];
         else v = s * (p * 1.0 + (1.0 - p) * 1.0);
         W.T[d + N] = v;
     }
-    for (int j = 1; j <= N; ++j) {
-        const double cp0 = (1.0 + gamma) * pow((double)j, gamma) - pow((double)j, gp1) + pow((double)(j - 1), gp1);
-        W.corr0[j] = s * p * cp0 - W.T[j + N];
-    }
-    for (int j = 0; j <= N - 1; ++j) {
-        const int m = N - j;
-        const double cmN = (1.0 + gamma) * pow((double)m, gamma) - pow((double)m, gp1) + pow((double)(m - 1), gp1);
-        W.corrN[j] = s * (1.0 - p) * cmN - W.T[(j - N) + N];
-    }
+    for (int j = 1; j <= N; ++j) W.corr0[j] = s * p * A.cp0[j] - W.T[j + N];
+    for (int j = 0; j <= N - 1; ++j) W.corrN[j] = s * (1.0 - p) * A.cmN[j] - W.T[(j - N) + N];
     return W;
 }
 
@@ -297,8 +311,7 @@ int check_device(lbm_fade* h)
 
 int run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s)
 {
-    for (int mu = 0; mu < h->dim; ++mu)
-        HIP_TRY(lbm::launch_fractional(h->ops[mu], h->lays[mu], h->params.precision, C, Phi + mu * h->nodes, s));
+    HIP_TRY(lbm::launch_fractional(h->ops, h->lays, h->dim, h->params.precision, C, Phi, h->nodes, s));
     return LBM_OK;
 }
 
@@ -488,6 +501,7 @@ int lbm_fade_set_C(lbm_fade_t h, const float* C0, int32_t on_device, void* strea
     HIP_TRY(lbm::launch_moment(h->cc, h->f[h->cur], h->C, s));
     if (!on_device) HIP_TRY(hipStreamSynchronize(s));  // the host buffer may be reused on return
     h->has_state = true;
+    h->at_initial_C = true;
     h->steps_done = 0;
     return LBM_OK;
 }
@@ -529,6 +543,7 @@ int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream)
         HIP_TRY(lbm::launch_collide_stream(h->cc, h->f[h->cur], h->f[1 - h->cur], h->Phi, h->S, h->C, s));
         h->cur = 1 - h->cur;
         h->steps_done += 1;
+        h->at_initial_C = false;
         if (every > 0 && h->steps_done % every == 0) {
             int flag = 0;
             HIP_TRY(hipMemsetAsync(h->flag, 0, sizeof(int), s));
@@ -579,6 +594,7 @@ int lbm_fade_set_f(lbm_fade_t h, const float* src, int32_t on_device, void* stre
     HIP_TRY(lbm::launch_moment(h->cc, h->f[h->cur], h->C, s));
     if (!on_device) HIP_TRY(hipStreamSynchronize(s));
     h->has_state = true;
+    h->at_initial_C = false;
     h->steps_done = 0;
     return LBM_OK;
 }

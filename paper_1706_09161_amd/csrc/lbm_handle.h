@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "../../include/lbm_fade.h"
 #include "lbm_internal.h"
@@ -27,6 +28,7 @@ struct lbm_fade {
     lbm::AxisLayout lays[3];
     lbm::CollideConsts cc;
     bool has_state = false;
+    bool at_initial_C = false;  // state is f^eq(C0) from set_C, no step taken since
     int64_t steps_done = 0;
     // FP64 host copies used by the adjoint
     double lam_bar[9] = {0};  // flux-block relaxation times lambda-bar
@@ -36,6 +38,14 @@ struct lbm_fade {
 };
 
 namespace lbm {
+// Product-rule coefficients of one axis (Sec. 2.4), FP64.
+struct AxisCoeffs {
+    double s;                // g dx^gamma / Gamma(2 + gamma)
+    std::vector<double> a;   // a_k, k = 0..N (a_0 = 1)
+    std::vector<double> cp0; // c+_{0j}, j = 1..N (index j; entry 0 unused)
+    std::vector<double> cmN; // c-_{Nj}, j = 0..N-1 (entry N unused)
+};
+AxisCoeffs axis_coeffs(int n, double gamma, double g, double dx);
 // Fractional term of every axis of C into Phi (d consecutive node fields).
 int fade_run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s);
 // Adjoint driver (adjoint.hip).

@@ -36,6 +36,18 @@ struct AxisLayout {
     int batches;           // strided case
 };
 
+// One launch of the fractional term for all axes of a step (workgroup ids
+// are split into per-axis ranges, axis 0 first).
+struct FracLaunch {
+    AxisOp op[3];
+    AxisLayout lay[3];
+    int tiles_m[3], tiles_n[3];
+    int first[4];  // first workgroup id of every axis, first[naxes] = grid size
+    const float* C;
+    float* Phi[3];
+    int naxes;
+};
+
 // Constants of the fused collide-stream kernel (Sec. 2.2-2.5).
 struct CollideConsts {
     int dim, Q;
@@ -48,8 +60,9 @@ struct CollideConsts {
 };
 
 // Kernel launchers (host functions).  All return a hipError_t.
-hipError_t launch_fractional(const AxisOp& op, const AxisLayout& lay, int precision, const float* C, float* Phi,
-                             hipStream_t s);
+// Fractional term of all axes: Phi + a * nodes receives axis a.
+hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
+                             float* Phi, int64_t nodes, hipStream_t s);
 hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
                                  const float* S, float* C_out, hipStream_t s);
 hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f,
@@ -58,5 +71,6 @@ hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t 
 hipError_t launch_moment(const CollideConsts& cc, const float* f, float* C, hipStream_t s);
 hipError_t launch_nonfinite_check(const float* C, int64_t nodes, int* flag, hipStream_t s);
 bool have_bf16x3();
+hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s);
 
 }  // namespace lbm
