@@ -98,6 +98,31 @@ def time_gemm(torch, solver, C_dev, reps: int) -> float:
     return start.elapsed_time(end) / 1e3 / reps
 
 
+def adjoint_ratio(torch, LbmFade, synth):
+    """Wall time of lbm_fade_adjoint(500 steps, checkpoint every 50) over that of
+    500 forward steps on the 512^2 adjoint workload (misfit gradient point)."""
+    cfg = synth.config("c5_512sq_eval")
+    steps, K = cfg["steps"], cfg["ckpt_every"]
+    C0 = torch.from_numpy(synth.initial_C(cfg).astype(np.float32)).cuda()
+    gC = torch.from_numpy(np.random.default_rng(5).standard_normal(synth.shape(cfg)).astype(np.float32)).cuda()
+    with LbmFade.from_config(cfg, precision="fp32") as s:
+        s.set_C(C0)
+        s.adjoint(steps, K, gC)  # warm-up (allocates checkpoints)
+        s.set_C(C0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        fwd = time.perf_counter() - t
+        s.set_C(C0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.adjoint(steps, K, gC)
+        adj = time.perf_counter() - t
+    return {"value": round(adj / fwd, 3), "adjoint_ms": adj * 1e3, "forward_ms": fwd * 1e3,
+            "workload": "2D 512x512 D2Q5 MRT, 500 steps, checkpoint every 50, FP32"}
+
+
 def cpu_baseline(cfg: dict, budget_s: float = 15.0):
     """The FP64 oracle as it stands, on the host's cores, for a bounded number of
     steps of the same workload (starting from its initial state)."""
@@ -206,6 +231,11 @@ def main():
                               "gemm_us_per_step": b["gemm_s"] * 1e6,
                               "gemm_mfma_TFLOPs_3terms": round(bach, 3),
                               "gemm_frac_of_bf16_peak": round(bach / PEAK["bf16_mfma_TFLOPs"], 4)}
+    try:
+        log("adjoint / forward")
+        line["adjoint_over_fwd"] = adjoint_ratio(torch, LbmFade, synth)
+    except Exception as e:  # reported, never fatal for the throughput line
+        line["adjoint_over_fwd"] = {"value": None, "error": str(e)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(cfg)

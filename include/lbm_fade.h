@@ -137,20 +137,25 @@ LBM_API int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t
 
 /* Gradients reported by lbm_fade_adjoint (FP64). */
 typedef struct {
-    double dD[9]; /* d x d, symmetric: d/dD_ab of the loss with D_ab = D_ba tied */
+    double dD[9]; /* d x d, symmetrised: dL = sum_ab dD_ab deltaD_ab for every symmetric
+                     perturbation deltaD (so dL/dD_01 with D_01 = D_10 tied is 2 dD_01);
+                     BGK: (dL/dD0 / d) Id for D = D0 Id */
     double du[3];
     double dp[3];
 } lbm_grads;
 
 /* Vector-Jacobian product of n steps (a hand-written adjoint; the paper has
- * none).  With C_n the concentration after n steps from the state given by
- * set_C (and the source given by set_source), returns the gradients of
- * L = <gC, C_n> with respect to D, u, p, the initial concentration (dC0, wall
- * entries zero; nullable) and the constant source (dS; nullable).  gC, dC0
- * and dS are host or device (same on_device), nodes floats each.  The forward
- * states are checkpointed every ckpt_every steps and recomputed per segment.
- * The solver state after the call is the state after n steps.  Synchronises
- * `stream` (the scalar gradients are written to host memory). */
+ * none).  With C_n the concentration after n steps from the current state
+ * (and the source given by set_source), returns the gradients of
+ * L = <gC, C_n> with respect to D, u, p, the constant source (dS; nullable)
+ * and, when the current state is the one set by set_C with no step since, the
+ * initial concentration (dC0, wall entries zero; nullable; LBM_ESTATE
+ * otherwise).  gC, dC0 and dS are host or device (same on_device), nodes
+ * floats each.  The forward states are checkpointed every ckpt_every steps
+ * and recomputed per segment; the GEMMs of the reverse sweep run in FP32
+ * whatever the handle's precision.  The solver state after the call is the
+ * state after n steps.  Synchronises `stream` (the scalar gradients are
+ * written to host memory). */
 LBM_API int lbm_fade_adjoint(lbm_fade_t h, int64_t n, int32_t ckpt_every, const float* gC, int32_t on_device,
                      lbm_grads* out, float* dC0, float* dS, void* stream);
 

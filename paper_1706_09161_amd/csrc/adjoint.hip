@@ -520,8 +520,8 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
             hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb, NV, A->acc, 0);
             ADJ_TRY(hipGetLastError());
             // fractional term reversed: K^T Phibar, and <Phibar, dK/dp C>
-            ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, A->kt, nodes, s));
-            ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C_j, A->psi, nodes, s));
+            ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nodes, A->kt, nodes, s));
+            ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C_j, 0, A->psi, nodes, s));
             if (d == 2) hipLaunchKernelGGL(dot_axes<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
             else hipLaunchKernelGGL(dot_axes<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
             ADJ_TRY(hipGetLastError());
@@ -544,8 +544,8 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     ADJ_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part, nb, d, A->acc, offU);
     ADJ_TRY(hipGetLastError());
-    ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, A->kt, nodes, s));
-    ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C0p, A->psi, nodes, s));
+    ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nodes, A->kt, nodes, s));
+    ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C0p, 0, A->psi, nodes, s));
     if (d == 2) hipLaunchKernelGGL(dot_axes<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
     else hipLaunchKernelGGL(dot_axes<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
     ADJ_TRY(hipGetLastError());

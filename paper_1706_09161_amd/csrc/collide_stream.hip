@@ -70,7 +70,9 @@ __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q]
 }
 
 // ---------------------------------------------------------------------------
-// 2D D2Q5 fused kernel.
+// 2D D2Q5 fused kernel.  The inputs of row y + 2 are requested before row y + 1
+// is collided and row y is written, so two rows of loads are in flight per
+// wavefront.
 template <bool HAS_S>
 __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
                                                          float* __restrict__ fout, const float* __restrict__ Phi,
@@ -89,35 +91,44 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
     const int y0 = chunk * rows_per_wave;
     const int y1 = min(ny, y0 + rows_per_wave);
 
-    auto collide_row = [&](int y, float (&fs)[5]) {
-        float f[5], phi[2], s = 0.f;
-        if (col_ok) {
+    struct Row {
+        float f[5], phi[2], s;
+    };
+    auto load_row = [&](int y, Row& r) {
+        if (col_ok && y >= 0 && y < ny) {
             const int64_t node = (int64_t)y * nx + x;
 #pragma unroll
-            for (int i = 0; i < 5; ++i) f[i] = fin[i * nodes + node];
-            phi[0] = Phi[node];
-            phi[1] = Phi[nodes + node];
-            if (HAS_S) s = S[node];
+            for (int i = 0; i < 5; ++i) r.f[i] = fin[i * nodes + node];
+            r.phi[0] = Phi[node];
+            r.phi[1] = Phi[nodes + node];
+            r.s = HAS_S ? S[node] : 0.f;
         } else {
 #pragma unroll
-            for (int i = 0; i < 5; ++i) f[i] = 0.f;
-            phi[0] = phi[1] = 0.f;
+            for (int i = 0; i < 5; ++i) r.f[i] = 0.f;
+            r.phi[0] = r.phi[1] = 0.f;
+            r.s = 0.f;
         }
-        collide_node<5>(cc, f, phi, s, fs);
     };
+    auto collide_row = [&](const Row& r, float (&fs)[5]) { collide_node<5>(cc, r.f, r.phi, r.s, fs); };
 
     float prev3 = 0.f;
     float cur[5], nxt[5];
+    Row ra, rb;
     if (y0 >= 1) {
+        load_row(y0 - 1, ra);
         float t[5];
-        collide_row(y0 - 1, t);
+        collide_row(ra, t);
         prev3 = t[3];
     }
-    collide_row(y0, cur);
+    load_row(y0, ra);
+    load_row(y0 + 1, rb);  // row y0 + 1 (zeros past the top wall)
+    collide_row(ra, cur);
     for (int y = y0; y < y1; ++y) {
         const bool has_next = (y + 1 < ny);
+        Row rc;
+        load_row(y + 2, rc);  // prefetch
         if (has_next) {
-            collide_row(y + 1, nxt);
+            collide_row(rb, nxt);
         } else {
 #pragma unroll
             for (int i = 0; i < 5; ++i) nxt[i] = 0.f;
@@ -153,6 +164,7 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
         prev3 = cur[3];
 #pragma unroll
         for (int i = 0; i < 5; ++i) cur[i] = nxt[i];
+        rb = rc;
     }
 }
 
@@ -185,35 +197,44 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
     __shared__ float sh3[NY][64];
     __shared__ float sh4[NY][64];
 
-    auto collide_at = [&](int z, float (&fs)[7]) {
-        float f[7], phi[3], s = 0.f;
-        if (ok) {
+    struct Plane {
+        float f[7], phi[3], s;
+    };
+    auto load_at = [&](int z, Plane& p) {
+        if (ok && z >= 0 && z < nz) {
             const int64_t node = (int64_t)z * plane + (int64_t)y * nx + x;
 #pragma unroll
-            for (int i = 0; i < 7; ++i) f[i] = fin[i * nodes + node];
+            for (int i = 0; i < 7; ++i) p.f[i] = fin[i * nodes + node];
 #pragma unroll
-            for (int mu = 0; mu < 3; ++mu) phi[mu] = Phi[mu * nodes + node];
-            if (HAS_S) s = S[node];
+            for (int mu = 0; mu < 3; ++mu) p.phi[mu] = Phi[mu * nodes + node];
+            p.s = HAS_S ? S[node] : 0.f;
         } else {
 #pragma unroll
-            for (int i = 0; i < 7; ++i) f[i] = 0.f;
-            phi[0] = phi[1] = phi[2] = 0.f;
+            for (int i = 0; i < 7; ++i) p.f[i] = 0.f;
+            p.phi[0] = p.phi[1] = p.phi[2] = 0.f;
+            p.s = 0.f;
         }
-        collide_node<7>(cc, f, phi, s, fs);
     };
+    auto collide_at = [&](const Plane& p, float (&fs)[7]) { collide_node<7>(cc, p.f, p.phi, p.s, fs); };
 
     float prev5 = 0.f;
     float cur[7], nxt[7];
+    Plane pa, pb;
     if (z0 >= 1) {
+        load_at(z0 - 1, pa);
         float t[7];
-        collide_at(z0 - 1, t);
+        collide_at(pa, t);
         prev5 = t[5];
     }
-    collide_at(z0, cur);
+    load_at(z0, pa);
+    load_at(z0 + 1, pb);
+    collide_at(pa, cur);
     for (int z = z0; z < z1; ++z) {
         const bool has_next = (z + 1 < nz);
+        Plane pc;
+        load_at(z + 2, pc);  // prefetch
         if (has_next) {
-            collide_at(z + 1, nxt);
+            collide_at(pb, nxt);
         } else {
 #pragma unroll
             for (int i = 0; i < 7; ++i) nxt[i] = 0.f;
@@ -254,6 +275,7 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
         prev5 = cur[5];
 #pragma unroll
         for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
+        pb = pc;
     }
 }
 
@@ -334,9 +356,12 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
     if (cc.dim == 2) {
         const int nx = cc.n[0], ny = cc.n[1];
         const int strips = (nx + kStrip - 1) / kStrip;
-        // enough wavefronts to fill the chip, long enough marches to amortise the halo rows
+        // Enough wavefronts to fill the chip about once (the march of one
+        // wavefront is a chain of dependent row loads, so parallelism across
+        // wavefronts hides the latency), long enough marches to amortise the
+        // two halo rows on large grids.
         int rows = 64;
-        while (rows > 8 && (int64_t)strips * ((ny + rows - 1) / rows) < 8 * 1024) rows /= 2;
+        while (rows > 2 && (int64_t)strips * ((ny + rows - 1) / rows) < 8 * 1024) rows /= 2;
         const int chunks = (ny + rows - 1) / rows;
         const int waves = strips * chunks;
         const unsigned blocks = (unsigned)((waves + 3) / 4);

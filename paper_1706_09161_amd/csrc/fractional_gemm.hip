@@ -18,6 +18,7 @@
 // In both cases the MFMA's lane-varying output index is the memory-contiguous
 // one, so stores are coalesced.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "lbm_internal.h"
@@ -152,7 +153,31 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
     static_assert(ELEMS % (kThreads * VEC) == 0, "tile not divisible");
     float stage[PER_THREAD][VEC];
 
+    // A chunk is "full" when all its lines and k are in range: then the loads
+    // need no per-element checks (uniform branch per chunk).
+    const bool lines_full = CONTIG ? ((int64_t)m0 + BM <= lines) : ((int64_t)n0 + BN <= lines);
     auto load_tile = [&](int k0) {
+        if constexpr (VEC == 4) {
+            if (lines_full && k0 + BK <= n) {
+#pragma unroll
+                for (int q = 0; q < PER_THREAD; ++q) {
+                    const int e = (q * kThreads + threadIdx.x) * VEC;
+                    float4 v;
+                    if constexpr (CONTIG) {
+                        const int r = e / BK, c = e % BK;
+                        v = *reinterpret_cast<const float4*>(Cb + ((int64_t)m0 + r) * n + k0 + c);
+                    } else {
+                        const int r = e / BN, c = e % BN;
+                        v = *reinterpret_cast<const float4*>(Cb + (int64_t)(k0 + r) * js + n0 + c);
+                    }
+                    stage[q][0] = v.x;
+                    stage[q][1] = v.y;
+                    stage[q][2] = v.z;
+                    stage[q][3] = v.w;
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
             const int e = (q * kThreads + threadIdx.x) * VEC;
@@ -232,9 +257,8 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
         const float* cur = (t & 1) ? tile1 : tile0;
         float* nxt = (t & 1) ? tile0 : tile1;
         if (t + 1 < nk) load_tile(k0 + BK);
-#pragma unroll
-        for (int kk = wk * KW; kk < wk * KW + KW; kk += 2) {
-            float a[MB], b[NB];
+        // operand fragments of k step kk (k = kk + lk within the chunk)
+        auto frags = [&](int kk, float (&a)[MB], float (&b)[NB]) {
             const int k = k0 + kk + lk;  // global k of this lane's operand element
             if constexpr (CONTIG) {
 #pragma unroll
@@ -247,11 +271,20 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
 #pragma unroll
                 for (int j = 0; j < NB; ++j) b[j] = cur[(kk + lk) * (BN + PADS) + colB + j * 32 + li];
             }
+        };
+        // fragments are read two k steps ahead of the MFMAs that use them
+        constexpr int NSTEP = KW / 2;
+        float a[3][MB], b[3][NB];
+        frags(wk * KW, a[0], b[0]);
+        if (NSTEP > 1) frags(wk * KW + 2, a[1], b[1]);
+#pragma unroll
+        for (int st = 0; st < NSTEP; ++st) {
+            if (st + 2 < NSTEP) frags(wk * KW + 2 * (st + 2), a[(st + 2) % 3], b[(st + 2) % 3]);
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
                 for (int j = 0; j < NB; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st % 3][i], b[st % 3][j], acc[i][j], 0, 0, 0);
         }
         if (t + 1 < nk) store_tile(nxt);
         __syncthreads();
@@ -333,11 +366,11 @@ __global__ __launch_bounds__(kThreads) void fractional_f32_mfma(FracLaunch L)
     const int local = bid - L.first[axis];
     const int total = L.first[axis + 1] - L.first[axis];
     if (axis == 0)
-        fractional_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C, L.Phi[0],
+        fractional_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C[0], L.Phi[0],
                                                                           L.tiles_m[0], L.tiles_n[0], local, total,
                                                                           smem);
     else
-        fractional_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_S>(L.op[axis], L.lay[axis], L.C,
+        fractional_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_S>(L.op[axis], L.lay[axis], L.C[axis],
                                                                            L.Phi[axis], L.tiles_m[axis],
                                                                            L.tiles_n[axis], local, total, smem);
 }
@@ -393,7 +426,7 @@ hipError_t run_f32(FracLaunch& L, hipStream_t s)
 }  // namespace
 
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
-                             float* Phi, int64_t nodes, hipStream_t s)
+                             int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s)
 {
     if (precision == 2) {
         for (int a = 0; a < naxes; ++a) {
@@ -401,7 +434,8 @@ hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxe
             const AxisLayout& lay = lays[a];
             const int64_t total = lay.contiguous ? lay.lines * op.n : (int64_t)lay.batches * op.n * lay.lines;
             const int64_t blocks = (total + 255) / 256;
-            hipLaunchKernelGGL(fractional_simt, dim3((unsigned)blocks), dim3(256), 0, s, op, lay, C, Phi + a * nodes);
+            hipLaunchKernelGGL(fractional_simt, dim3((unsigned)blocks), dim3(256), 0, s, op, lay, C + a * in_stride,
+                               Phi + a * nodes);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -409,33 +443,48 @@ hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxe
     }
     FracLaunch L;
     memset(&L, 0, sizeof(L));
-    if (precision == 1) {
-        L.naxes = naxes;
-        L.C = C;
-        for (int a = 0; a < naxes; ++a) {
-            L.op[a] = ops[a];
-            L.lay[a] = lays[a];
-            L.Phi[a] = Phi + a * nodes;
-        }
-        return launch_fractional_bf16x3(L, s);
-    }
     L.naxes = naxes;
-    L.C = C;
     for (int a = 0; a < naxes; ++a) {
         L.op[a] = ops[a];
         L.lay[a] = lays[a];
+        L.C[a] = C + a * in_stride;
         L.Phi[a] = Phi + a * nodes;
     }
-    // work in units of 128 x 128 output tiles: below ~2 per CU, use the small
-    // split-K tiles
-    int64_t big_tiles = 0;
-    for (int a = 0; a < naxes; ++a) {
-        const int64_t m = lays[a].contiguous ? lays[a].lines : ops[a].n;
-        const int64_t nn = lays[a].contiguous ? ops[a].n : lays[a].lines * lays[a].batches;
-        big_tiles += ((m + 127) / 128) * ((nn + 127) / 128);
+    if (precision == 1) return launch_fractional_bf16x3(L, s);
+    // Tile configuration: LBM_FP32_TILE (read once) selects one explicitly, for
+    // tuning; by default the work is counted in 128 x 128 output tiles and
+    // grids below ~2 such tiles per CU use the small split-K tiles.
+    switch (tile_choice("LBM_FP32_TILE")) {
+    case 1: return run_f32<64, 64, 64, 1, 1, 4>(L, s);
+    case 2: return run_f32<64, 64, 128, 1, 1, 4>(L, s);
+    case 3: return run_f32<128, 64, 64, 2, 1, 2>(L, s);
+    case 4: return run_f32<64, 128, 64, 1, 2, 2>(L, s);
+    case 5: return run_f32<128, 128, 32, 2, 2, 1>(L, s);
+    case 6: return run_f32<128, 128, 64, 2, 2, 1>(L, s);
+    default: break;
     }
-    if (big_tiles < 512) return run_f32<64, 64, 64, 1, 1, 4>(L, s);
+    if (big_tiles(L) < 512) return run_f32<64, 64, 128, 1, 1, 4>(L, s);
     return run_f32<128, 128, 32, 2, 2, 1>(L, s);
+}
+
+int64_t big_tiles(const FracLaunch& L)
+{
+    int64_t t = 0;
+    for (int a = 0; a < L.naxes; ++a) {
+        const int64_t m = L.lay[a].contiguous ? L.lay[a].lines : L.op[a].n;
+        const int64_t nn = L.lay[a].contiguous ? L.op[a].n : L.lay[a].lines * L.lay[a].batches;
+        t += ((m + 127) / 128) * ((nn + 127) / 128);
+    }
+    return t;
+}
+
+int tile_choice(const char* var)
+{
+    // 0 = automatic; 1..6 = the explicit configurations listed at the call sites
+    const char* v = getenv(var);
+    if (!v || !*v) return 0;
+    const int c = atoi(v);
+    return (c >= 1 && c <= 6) ? c : 0;
 }
 
 }  // namespace lbm

@@ -318,10 +318,10 @@ __global__ __launch_bounds__(kThreads) void fractional_bf16x3_mfma(FracLaunch L)
     const int local = bid - L.first[axis];
     const int total = L.first[axis + 1] - L.first[axis];
     if (axis == 0)
-        bf16x3_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C, L.Phi[0], L.tiles_m[0],
+        bf16x3_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C[0], L.Phi[0], L.tiles_m[0],
                                                                        L.tiles_n[0], local, total, smem_b);
     else
-        bf16x3_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1>(L.op[axis], L.lay[axis], L.C, L.Phi[axis],
+        bf16x3_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1>(L.op[axis], L.lay[axis], L.C[axis], L.Phi[axis],
                                                                     L.tiles_m[axis], L.tiles_n[axis], local, total,
                                                                     smem_b);
 }
@@ -375,13 +375,17 @@ bool have_bf16x3() { return true; }
 
 hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s)
 {
-    int64_t big_tiles = 0;
-    for (int a = 0; a < L.naxes; ++a) {
-        const int64_t m = L.lay[a].contiguous ? L.lay[a].lines : L.op[a].n;
-        const int64_t nn = L.lay[a].contiguous ? L.op[a].n : L.lay[a].lines * L.lay[a].batches;
-        big_tiles += ((m + 127) / 128) * ((nn + 127) / 128);
+    // LBM_BF16_TILE selects a configuration explicitly (tuning); see launch_fractional.
+    switch (tile_choice("LBM_BF16_TILE")) {
+    case 1: return run_bf16<64, 64, 64, 1, 1, 4>(L, s);
+    case 2: return run_bf16<64, 64, 128, 1, 1, 4>(L, s);
+    case 3: return run_bf16<128, 64, 64, 2, 1, 2>(L, s);
+    case 4: return run_bf16<64, 128, 64, 1, 2, 2>(L, s);
+    case 5: return run_bf16<128, 128, 32, 2, 2, 1>(L, s);
+    case 6: return run_bf16<128, 128, 64, 2, 2, 1>(L, s);
+    default: break;
     }
-    if (big_tiles < 512) return run_bf16<64, 64, 64, 1, 1, 4>(L, s);
+    if (big_tiles(L) < 512) return run_bf16<64, 64, 64, 1, 1, 4>(L, s);
     return run_bf16<128, 128, 32, 2, 2, 1>(L, s);
 }
 

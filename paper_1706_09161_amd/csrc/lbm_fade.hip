@@ -311,7 +311,7 @@ int check_device(lbm_fade* h)
 
 int run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s)
 {
-    HIP_TRY(lbm::launch_fractional(h->ops, h->lays, h->dim, h->params.precision, C, Phi, h->nodes, s));
+    HIP_TRY(lbm::launch_fractional(h->ops, h->lays, h->dim, h->params.precision, C, 0, Phi, h->nodes, s));
     return LBM_OK;
 }
 

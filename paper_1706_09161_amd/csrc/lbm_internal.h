@@ -43,7 +43,7 @@ struct FracLaunch {
     AxisLayout lay[3];
     int tiles_m[3], tiles_n[3];
     int first[4];  // first workgroup id of every axis, first[naxes] = grid size
-    const float* C;
+    const float* C[3];  // input field of every axis
     float* Phi[3];
     int naxes;
 };
@@ -60,9 +60,10 @@ struct CollideConsts {
 };
 
 // Kernel launchers (host functions).  All return a hipError_t.
-// Fractional term of all axes: Phi + a * nodes receives axis a.
+// Fractional term of all axes: axis a reads C + a * in_stride (in_stride = 0:
+// one field for every axis) and writes Phi + a * nodes.
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
-                             float* Phi, int64_t nodes, hipStream_t s);
+                             int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s);
 hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
                                  const float* S, float* C_out, hipStream_t s);
 hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f,
@@ -71,6 +72,10 @@ hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t 
 hipError_t launch_moment(const CollideConsts& cc, const float* f, float* C, hipStream_t s);
 hipError_t launch_nonfinite_check(const float* C, int64_t nodes, int* flag, hipStream_t s);
 bool have_bf16x3();
+// Output tiles of 128 x 128 over all axes (sizes the GEMM launch).
+int64_t big_tiles(const FracLaunch& L);
+// Tile configuration forced through an environment variable (0 = automatic).
+int tile_choice(const char* var);
 hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s);
 
 }  // namespace lbm
