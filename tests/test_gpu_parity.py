@@ -268,3 +268,31 @@ def test_zero_steps_and_repeat_calls_are_consistent():
     ref0 = oracle.moment(cfg, oracle.init(cfg, C0.astype(np.float64)))
     assert np.abs(a - ref0).max() < 1e-5
     assert np.array_equal(b, c)  # deterministic
+
+
+@pytest.mark.parametrize("name,precision,bound", [("c2_1024sq", "fp32", 1e-5), ("c2_1024sq", "bf16x3", 1e-4),
+                                                  ("c3_256cube", "fp32", 1e-5), ("c3_256cube", "bf16x3", 1e-4)])
+def test_full_workload_against_stored_oracle(name, precision, bound):
+    """The workloads at full size and full step count (1024^2 x 2000 steps;
+    256^3 x 500 steps with its point source) against the stored FP64 oracle
+    result (every 4th node in 2D, every 8th in 3D; tests/golden/make_reference.py)."""
+    import os
+
+    from conftest import GOLDEN
+
+    cfg = synth.config(name)
+    stride = 4 if cfg["dim"] == 2 else 8
+    path = os.path.join(GOLDEN, f"ref_{name}_{cfg['steps']}steps_every{stride}.npz")
+    ref = np.load(path)
+    _banner(f"full workload {name} {precision}")
+    S = synth.source(cfg)
+    with _solver(cfg, precision) as s:
+        s.set_C(synth.initial_C(cfg).astype(np.float32))
+        if S is not None:
+            s.set_source(S.astype(np.float32))
+        s.step(cfg["steps"])
+        C = s.get_C(device=False)
+    sl = (slice(None, None, stride),) * cfg["dim"]
+    err = _rel_l2(C[sl], ref["C"])
+    print(f"[gpu-parity] {name} {precision} rel L2 vs stored oracle = {err:.3e}", flush=True)
+    assert err <= bound
