@@ -473,15 +473,11 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     for (int64_t t = 0; t < n; ++t) {
         if (t % K == 0) ADJ_TRY(hipMemcpyAsync(A->ckpt + (t / K) * Q * nodes, h->f[h->cur], fq,
                                                hipMemcpyDeviceToDevice, s));
-        int rc = fade_run_phi(h, h->C, h->Phi, s);
+        int rc = fade_forward_step(h, s);
         if (rc) {
-            msg = "forward fractional term failed";
+            msg = "forward step failed";
             return rc;
         }
-        ADJ_TRY(launch_collide_stream(h->cc, h->f[h->cur], h->f[1 - h->cur], h->Phi, h->S, h->C, s));
-        h->cur = 1 - h->cur;
-        h->steps_done += 1;
-        h->at_initial_C = false;
     }
     if (n == 0) ADJ_TRY(hipMemcpyAsync(A->ckpt, h->f[h->cur], fq, hipMemcpyDeviceToDevice, s));
     // --- reverse sweep
@@ -505,7 +501,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
             }
             if (j + 1 < len)
                 ADJ_TRY(launch_collide_stream(h->cc, f_at(j), A->seg_f + (int64_t)(j + 1) * Q * nodes, phi_j, h->S,
-                                              A->seg_C + (int64_t)(j + 1) * nodes, s));
+                                              A->seg_C + (int64_t)(j + 1) * nodes, nullptr, s));
         }
         for (int j = len - 1; j >= 0; --j) {
             const float* phi_j = A->seg_phi + (int64_t)j * d * nodes;
@@ -520,8 +516,8 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
             hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb, NV, A->acc, 0);
             ADJ_TRY(hipGetLastError());
             // fractional term reversed: K^T Phibar, and <Phibar, dK/dp C>
-            ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nodes, A->kt, nodes, s));
-            ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C_j, 0, A->psi, nodes, s));
+            ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nullptr, nodes, A->kt, nodes, s));
+            ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C_j, nullptr, 0, A->psi, nodes, s));
             if (d == 2) hipLaunchKernelGGL(dot_axes<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
             else hipLaunchKernelGGL(dot_axes<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
             ADJ_TRY(hipGetLastError());
@@ -544,8 +540,8 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     ADJ_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part, nb, d, A->acc, offU);
     ADJ_TRY(hipGetLastError());
-    ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nodes, A->kt, nodes, s));
-    ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C0p, 0, A->psi, nodes, s));
+    ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nullptr, nodes, A->kt, nodes, s));
+    ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C0p, nullptr, 0, A->psi, nodes, s));
     if (d == 2) hipLaunchKernelGGL(dot_axes<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
     else hipLaunchKernelGGL(dot_axes<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
     ADJ_TRY(hipGetLastError());

@@ -28,6 +28,7 @@
 // (one wave per y row, rows 0 and NY-1 halo) and marches along z; f*_3/f*_4
 // cross rows through LDS, f*_5/f*_6 cross planes in registers.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 
 #include "lbm_internal.h"
 
@@ -35,6 +36,20 @@ namespace lbm {
 namespace {
 
 constexpr int kStrip = 62;  // output columns per wavefront (64 lanes minus 2 halo)
+
+// BF16 split of C for the split-BF16 fractional term: hi = bf16(c),
+// lo = bf16(c - hi), both round to nearest even, packed hi | lo << 16.
+__device__ __forceinline__ uint32_t bf16_bits(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint32_t pack_hilo(float c)
+{
+    const uint32_t hi = bf16_bits(c);
+    const uint32_t lo = bf16_bits(c - __uint_as_float(hi << 16));
+    return hi | (lo << 16);
+}
 
 template <int Q>
 __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
@@ -73,11 +88,12 @@ __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q]
 // 2D D2Q5 fused kernel.  The inputs of row y + 2 are requested before row y + 1
 // is collided and row y is written, so two rows of loads are in flight per
 // wavefront.
-template <bool HAS_S>
+template <bool HAS_S, bool PACK>
 __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
                                                          float* __restrict__ fout, const float* __restrict__ Phi,
                                                          const float* __restrict__ S, float* __restrict__ Cout,
-                                                         int rows_per_wave, int strips, int total_waves)
+                                                         uint32_t* __restrict__ Cpout, int rows_per_wave,
+                                                         int strips, int total_waves)
 {
     const int nx = cc.n[0], ny = cc.n[1];
     const int64_t nodes = (int64_t)nx * ny;
@@ -160,6 +176,7 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
                 c += f[i];
             }
             Cout[node] = c;
+            if (PACK) Cpout[node] = pack_hilo(c);
         }
         prev3 = cur[3];
 #pragma unroll
@@ -171,11 +188,12 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
 // ---------------------------------------------------------------------------
 // 3D D3Q7 fused kernel: workgroup = NY wavefronts (one per y row), rows 0 and
 // NY-1 of the workgroup are halo rows; marches along z.
-template <int NY, bool HAS_S>
+template <int NY, bool HAS_S, bool PACK>
 __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, const float* __restrict__ fin,
                                                              float* __restrict__ fout, const float* __restrict__ Phi,
                                                              const float* __restrict__ S, float* __restrict__ Cout,
-                                                             int planes_per_block, int strips_x, int strips_y)
+                                                             uint32_t* __restrict__ Cpout, int planes_per_block,
+                                                             int strips_x, int strips_y)
 {
     const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
     const int64_t plane = (int64_t)nx * ny;
@@ -270,6 +288,7 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
                 c += f[i];
             }
             Cout[node] = c;
+            if (PACK) Cpout[node] = pack_hilo(c);
         }
         __syncthreads();  // sh3/sh4 are rewritten in the next plane
         prev5 = cur[5];
@@ -331,6 +350,12 @@ __global__ void moment_kernel(const float* __restrict__ f, float* __restrict__ C
     C[x] = c;
 }
 
+__global__ void pack_kernel(const float* __restrict__ C, uint32_t* __restrict__ Cp, int64_t count)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < count) Cp[x] = pack_hilo(C[x]);
+}
+
 __global__ void nonfinite_kernel(const float* __restrict__ C, int64_t nodes, int* flag)
 {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,29 +373,42 @@ int64_t nodes_of(const CollideConsts& cc)
 
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Rows per wavefront of the 2D kernel forced by LBM_COLLIDE_ROWS (tuning; 0 = automatic).
+int collide_rows_override()
+{
+    const char* e = getenv("LBM_COLLIDE_ROWS");
+    const int r = e ? atoi(e) : 0;
+    return (r >= 1 && r <= 1024) ? r : 0;
+}
+
 }  // namespace
 
 hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
-                                 const float* S, float* C_out, hipStream_t s)
+                                 const float* S, float* C_out, uint32_t* Cp_out, hipStream_t s)
 {
     if (cc.dim == 2) {
         const int nx = cc.n[0], ny = cc.n[1];
         const int strips = (nx + kStrip - 1) / kStrip;
-        // Enough wavefronts to fill the chip about once (the march of one
-        // wavefront is a chain of dependent row loads, so parallelism across
-        // wavefronts hides the latency), long enough marches to amortise the
-        // two halo rows on large grids.
-        int rows = 64;
-        while (rows > 2 && (int64_t)strips * ((ny + rows - 1) / rows) < 8 * 1024) rows /= 2;
+        // Rows per wavefront: short marches leave more wavefronts to hide the
+        // latency of each row's loads, long ones amortise the two halo rows.
+        // Measured best on MI355X: 4 rows up to 512 rows of grid, 16 while the
+        // state stays in the Infinity Cache (up to 4 M nodes), 8 beyond.
+        int rows = collide_rows_override();
+        if (rows <= 0) rows = ny <= 512 ? 4 : ((int64_t)nx * ny <= (1 << 22) ? 16 : 8);
         const int chunks = (ny + rows - 1) / rows;
         const int waves = strips * chunks;
         const unsigned blocks = (unsigned)((waves + 3) / 4);
-        if (S)
-            hipLaunchKernelGGL(collide_stream_2d<true>, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out,
-                               rows, strips, waves);
-        else
-            hipLaunchKernelGGL(collide_stream_2d<false>, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S,
-                               C_out, rows, strips, waves);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out, rows,
+                               strips, waves);
+        };
+        if (S) {
+            if (Cp_out) go(collide_stream_2d<true, true>);
+            else go(collide_stream_2d<true, false>);
+        } else {
+            if (Cp_out) go(collide_stream_2d<false, true>);
+            else go(collide_stream_2d<false, false>);
+        }
         return hipGetLastError();
     }
     constexpr int NY = 8;
@@ -382,12 +420,23 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
     const int chunks = (nz + planes - 1) / planes;
     const int64_t blocks = (int64_t)sx * sy * chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (S)
-        hipLaunchKernelGGL((collide_stream_3d<NY, true>), dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out,
-                           Phi, S, C_out, planes, sx, sy);
-    else
-        hipLaunchKernelGGL((collide_stream_3d<NY, false>), dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in,
-                           f_out, Phi, S, C_out, planes, sx, sy);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out,
+                           planes, sx, sy);
+    };
+    if (S) {
+        if (Cp_out) go(collide_stream_3d<NY, true, true>);
+        else go(collide_stream_3d<NY, true, false>);
+    } else {
+        if (Cp_out) go(collide_stream_3d<NY, false, true>);
+        else go(collide_stream_3d<NY, false, false>);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16(const float* C, uint32_t* Cp, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, C, Cp, count);
     return hipGetLastError();
 }
 

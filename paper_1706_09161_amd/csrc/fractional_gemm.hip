@@ -280,11 +280,15 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
 #pragma unroll
         for (int st = 0; st < NSTEP; ++st) {
             if (st + 2 < NSTEP) frags(wk * KW + 2 * (st + 2), a[(st + 2) % 3], b[(st + 2) % 3]);
+            // keep the reads of step st + 2 ahead of the MFMAs of step st (the
+            // scheduler would otherwise sink them next to their use)
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
                 for (int j = 0; j < NB; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st % 3][i], b[st % 3][j], acc[i][j], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (t + 1 < nk) store_tile(nxt);
         __syncthreads();
@@ -426,7 +430,7 @@ hipError_t run_f32(FracLaunch& L, hipStream_t s)
 }  // namespace
 
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
-                             int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s)
+                             const uint32_t* Cp, int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s)
 {
     if (precision == 2) {
         for (int a = 0; a < naxes; ++a) {
@@ -448,9 +452,13 @@ hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxe
         L.op[a] = ops[a];
         L.lay[a] = lays[a];
         L.C[a] = C + a * in_stride;
+        L.Cp[a] = Cp ? Cp + a * in_stride : nullptr;
         L.Phi[a] = Phi + a * nodes;
     }
-    if (precision == 1) return launch_fractional_bf16x3(L, s);
+    if (precision == 1) {
+        if (!Cp) return hipErrorInvalidValue;
+        return launch_fractional_bf16x3(L, s);
+    }
     // Tile configuration: LBM_FP32_TILE (read once) selects one explicitly, for
     // tuning; by default the work is counted in 128 x 128 output tiles and
     // grids below ~2 such tiles per CU use the small split-K tiles.

@@ -6,7 +6,8 @@
 // with x_hi = bf16(x) and x_lo = bf16(x - x_hi) (round to nearest even):
 //   K C  ~  K_hi C_hi + K_hi C_lo + K_lo C_hi     (the K_lo C_lo term is dropped).
 // The Toeplitz weights are split on the host from their FP64 values; C is
-// split in FP32 while it is staged into LDS.  Each dropped or rounded piece
+// split once per step by its producer (the collide-stream kernel, or a pack
+// kernel) into one packed word per node, which the staging only regroups.  Each dropped or rounded piece
 // is of relative size 2^-16 or below, against 2^-24 for FP32 operands, for a
 // 16 x (3 MFMA) rate advantage per product term over FP32 MFMA.
 //
@@ -36,25 +37,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 
-// Round-to-nearest-even FP32 -> BF16 bits (inputs are finite here).
-__device__ __forceinline__ uint32_t bf16_rne_bits(float x)
-{
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-
-// split x into (hi, lo) BF16 bit patterns
-__device__ __forceinline__ void split2(float x, uint32_t& hi, uint32_t& lo)
-{
-    hi = bf16_rne_bits(x);
-    const float r = x - __uint_as_float(hi << 16);  // exact
-    lo = bf16_rne_bits(r);
-}
-
 template <bool CONTIG, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int KSPLIT, int VEC>
 __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& lay, const float* __restrict__ C,
-                                            float* __restrict__ Phi, int tiles_m, int tiles_n, int bid, int total,
-                                            unsigned char* smem)
+                                            const uint32_t* __restrict__ Cp, float* __restrict__ Phi, int tiles_m,
+                                            int tiles_n, int bid, int total, unsigned char* smem)
 {
     static_assert(WAVES_M * WAVES_N * KSPLIT == kWaves, "4 wavefronts per workgroup");
     static_assert(BM == WAVES_M * 64 && BN == WAVES_N * 64, "64 x 64 per wavefront");
@@ -100,18 +86,21 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
 
     const int64_t lines = lay.lines;
     const float* Cb = C;
+    const uint32_t* Cpb = Cp;
     float* Pb = Phi;
     if (!CONTIG) {
         Cb += (int64_t)batch * lay.batch_stride;
+        Cpb += (int64_t)batch * lay.batch_stride;
         Pb += (int64_t)batch * lay.batch_stride;
     }
     const int64_t js = lay.j_stride;
 
-    // ---- staging: groups of 8 consecutive k of one line
+    // ---- staging: groups of 8 consecutive k of one line, read as packed
+    // (hi | lo << 16) words and regrouped into a hi and a lo BF16 row
     constexpr int GROUPS = CROWS * (BK / 8);
     constexpr int GPT = GROUPS / kThreads;
     static_assert(GROUPS % kThreads == 0, "tile not divisible");
-    float stage[GPT][8];
+    uint32_t stage[GPT][8];
 
     auto load_tile = [&](int k0) {
 #pragma unroll
@@ -123,28 +112,25 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                 const int k = k0 + 8 * g;
                 if constexpr (VEC == 4) {
                     if (line < lines && k + 7 < n) {
-                        const float4 v0 = *reinterpret_cast<const float4*>(Cb + line * n + k);
-                        const float4 v1 = *reinterpret_cast<const float4*>(Cb + line * n + k + 4);
-                        stage[q][0] = v0.x;
-                        stage[q][1] = v0.y;
-                        stage[q][2] = v0.z;
-                        stage[q][3] = v0.w;
-                        stage[q][4] = v1.x;
-                        stage[q][5] = v1.y;
-                        stage[q][6] = v1.z;
-                        stage[q][7] = v1.w;
+                        const u32x4 v0 = *reinterpret_cast<const u32x4*>(Cpb + line * n + k);
+                        const u32x4 v1 = *reinterpret_cast<const u32x4*>(Cpb + line * n + k + 4);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            stage[q][e] = v0[e];
+                            stage[q][4 + e] = v1[e];
+                        }
                         continue;
                     }
                 }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) stage[q][e] = (line < lines && k + e < n) ? Cb[line * n + k + e] : 0.f;
+                for (int e = 0; e < 8; ++e) stage[q][e] = (line < lines && k + e < n) ? Cpb[line * n + k + e] : 0u;
             } else {
                 const int row = id % BN, g = id / BN;
                 const int64_t line = (int64_t)n0 + row;
                 const int k = k0 + 8 * g;
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                    stage[q][e] = (line < lines && k + e < n) ? Cb[(int64_t)(k + e) * js + line] : 0.f;
+                    stage[q][e] = (line < lines && k + e < n) ? Cpb[(int64_t)(k + e) * js + line] : 0u;
             }
         }
     };
@@ -162,14 +148,12 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                 row = id % BN;
                 g = id / BN;
             }
-            uint32_t h[8], l[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) split2(stage[q][e], h[e], l[e]);
             u32x4 hv, lv;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                hv[p] = h[2 * p] | (h[2 * p + 1] << 16);
-                lv[p] = l[2 * p] | (l[2 * p + 1] << 16);
+                const uint32_t w0 = stage[q][2 * p], w1 = stage[q][2 * p + 1];
+                hv[p] = (w0 & 0xffffu) | (w1 << 16);
+                lv[p] = (w0 >> 16) | (w1 & 0xffff0000u);
             }
             *reinterpret_cast<u32x4*>(hi + row * RS + 8 * g) = hv;
             *reinterpret_cast<u32x4*>(lo + row * RS + 8 * g) = lv;
@@ -198,18 +182,18 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
         const uint16_t* chi = ctile + (2 * buf) * CT;
         const uint16_t* clo = ctile + (2 * buf + 1) * CT;
         if (t + 1 < nk) load_tile(k0 + BK);
-#pragma unroll
-        for (int ks = wk * KW; ks < wk * KW + KW; ks += 16) {
+        struct Frags {
+            bf16x8 c_hi[2], c_lo[2], t_hi[2], t_lo[2];
+        };
+        auto frags = [&](int ks, Frags& F) {
             // C-tile fragments (A in the contiguous case, B otherwise)
-            bf16x8 c_hi[2], c_lo[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int row = ctBase + b * 32 + li;
-                c_hi[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(chi + row * RS + ks + 8 * lk));
-                c_lo[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(clo + row * RS + ks + 8 * lk));
+                F.c_hi[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(chi + row * RS + ks + 8 * lk));
+                F.c_lo[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(clo + row * RS + ks + 8 * lk));
             }
             // Toeplitz fragments: T(r - k) for k = k0 + ks + 8*lk + e, e = 0..7
-            bf16x8 t_hi[2], t_lo[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int r = toepBase + b * 32 + li;
@@ -223,9 +207,18 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                     hv[p] = (w[2 * p] & 0xffffu) | (w[2 * p + 1] << 16);
                     lv[p] = (w[2 * p] >> 16) | (w[2 * p + 1] & 0xffff0000u);
                 }
-                t_hi[b] = __builtin_bit_cast(bf16x8, hv);
-                t_lo[b] = __builtin_bit_cast(bf16x8, lv);
+                F.t_hi[b] = __builtin_bit_cast(bf16x8, hv);
+                F.t_lo[b] = __builtin_bit_cast(bf16x8, lv);
             }
+        };
+        constexpr int NSTEP = KW / 16;
+        Frags F[2];
+        frags(wk * KW, F[0]);
+#pragma unroll
+        for (int st = 0; st < NSTEP; ++st) {
+            if (st + 1 < NSTEP) frags(wk * KW + 16 * (st + 1), F[(st + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);  // reads of the next step stay ahead of these MFMAs
+            const Frags& G = F[st & 1];
             // CONTIG: A = C tile (block i), B = Toeplitz (block j); else A = Toeplitz (i), B = C (j).
             // Small terms first; consecutive MFMAs go to different accumulators.
 #pragma unroll
@@ -234,14 +227,15 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
                     for (int j = 0; j < NB; ++j) {
-                        const bf16x8 ah = CONTIG ? c_hi[i] : t_hi[i];
-                        const bf16x8 al = CONTIG ? c_lo[i] : t_lo[i];
-                        const bf16x8 bh = CONTIG ? t_hi[j] : c_hi[j];
-                        const bf16x8 bl = CONTIG ? t_lo[j] : c_lo[j];
+                        const bf16x8 ah = CONTIG ? G.c_hi[i] : G.t_hi[i];
+                        const bf16x8 al = CONTIG ? G.c_lo[i] : G.t_lo[i];
+                        const bf16x8 bh = CONTIG ? G.t_hi[j] : G.c_hi[j];
+                        const bf16x8 bl = CONTIG ? G.t_lo[j] : G.c_lo[j];
                         const bf16x8 a = term == 0 ? al : ah;
                         const bf16x8 b = term == 1 ? bl : bh;
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i][j], 0, 0, 0);
                     }
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (t + 1 < nk) store_tile(buf ^ 1);
         __syncthreads();
@@ -318,10 +312,12 @@ __global__ __launch_bounds__(kThreads) void fractional_bf16x3_mfma(FracLaunch L)
     const int local = bid - L.first[axis];
     const int total = L.first[axis + 1] - L.first[axis];
     if (axis == 0)
-        bf16x3_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C[0], L.Phi[0], L.tiles_m[0],
+        bf16x3_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C[0], L.Cp[0], L.Phi[0],
+                                                                       L.tiles_m[0],
                                                                        L.tiles_n[0], local, total, smem_b);
     else
-        bf16x3_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1>(L.op[axis], L.lay[axis], L.C[axis], L.Phi[axis],
+        bf16x3_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1>(L.op[axis], L.lay[axis], L.C[axis], L.Cp[axis],
+                                                                    L.Phi[axis],
                                                                     L.tiles_m[axis], L.tiles_n[axis], local, total,
                                                                     smem_b);
 }
@@ -385,7 +381,7 @@ hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s)
     case 6: return run_bf16<128, 128, 64, 2, 2, 1>(L, s);
     default: break;
     }
-    if (big_tiles(L) < 512) return run_bf16<64, 64, 64, 1, 1, 4>(L, s);
+    if (big_tiles(L) < 512) return run_bf16<64, 64, 128, 1, 1, 4>(L, s);
     return run_bf16<128, 128, 32, 2, 2, 1>(L, s);
 }
 

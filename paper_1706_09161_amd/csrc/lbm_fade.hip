@@ -311,7 +311,35 @@ int check_device(lbm_fade* h)
 
 int run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s)
 {
-    HIP_TRY(lbm::launch_fractional(h->ops, h->lays, h->dim, h->params.precision, C, 0, Phi, h->nodes, s));
+    const uint32_t* Cp = nullptr;
+    if (h->params.precision == LBM_BF16X3) {
+        if (C == h->C) {
+            Cp = h->Cp;  // kept in sync by set_C / set_f / the collide-stream kernel
+        } else {
+            HIP_TRY(lbm::launch_pack_bf16(C, h->Cp_tmp, h->nodes, s));
+            Cp = h->Cp_tmp;
+        }
+    }
+    HIP_TRY(lbm::launch_fractional(h->ops, h->lays, h->dim, h->params.precision, C, Cp, 0, Phi, h->nodes, s));
+    return LBM_OK;
+}
+
+int forward_step(lbm_fade* h, hipStream_t s)
+{
+    int rc = run_phi(h, h->C, h->Phi, s);
+    if (rc) return rc;
+    HIP_TRY(lbm::launch_collide_stream(h->cc, h->f[h->cur], h->f[1 - h->cur], h->Phi, h->S, h->C, h->Cp, s));
+    h->cur = 1 - h->cur;
+    h->steps_done += 1;
+    h->at_initial_C = false;
+    return LBM_OK;
+}
+
+// C := sum_i f_i of the current populations (and its BF16 split)
+int refresh_C(lbm_fade* h, hipStream_t s)
+{
+    HIP_TRY(lbm::launch_moment(h->cc, h->f[h->cur], h->C, s));
+    if (h->Cp) HIP_TRY(lbm::launch_pack_bf16(h->C, h->Cp, h->nodes, s));
     return LBM_OK;
 }
 
@@ -320,6 +348,7 @@ int run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s)
 namespace lbm {
 // used by the adjoint driver
 int fade_run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s) { return run_phi(h, C, Phi, s); }
+int fade_forward_step(lbm_fade* h, hipStream_t s) { return forward_step(h, s); }
 }  // namespace lbm
 
 extern "C" {
@@ -467,6 +496,12 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
         cleanup();
         return fail(LBM_ENOMEM, "hipMalloc of the solver state failed");
     }
+    if (params->precision == LBM_BF16X3 &&
+        (hipMalloc(&h->Cp, sizeof(uint32_t) * h->nodes) != hipSuccess ||
+         hipMalloc(&h->Cp_tmp, sizeof(uint32_t) * h->nodes) != hipSuccess)) {
+        cleanup();
+        return fail(LBM_ENOMEM, "hipMalloc of the BF16 split of C failed");
+    }
     *out = h;
     g_error.clear();
     return LBM_OK;
@@ -482,6 +517,8 @@ void lbm_fade_destroy(lbm_fade_t h)
     (void)hipFree(h->C);
     (void)hipFree(h->Phi);
     (void)hipFree(h->S);
+    (void)hipFree(h->Cp);
+    (void)hipFree(h->Cp_tmp);
     (void)hipFree(h->opmem);
     (void)hipFree(h->flag);
     delete h;
@@ -495,10 +532,12 @@ int lbm_fade_set_C(lbm_fade_t h, const float* C0, int32_t on_device, void* strea
     hipStream_t s = as_stream(stream);
     HIP_TRY(hipMemcpyAsync(h->C, C0, sizeof(float) * h->nodes, kind_to_dev(on_device), s));
     HIP_TRY(lbm::launch_wall_overwrite(h->cc, h->C, s));
+    if (h->Cp) HIP_TRY(lbm::launch_pack_bf16(h->C, h->Cp, h->nodes, s));
     rc = run_phi(h, h->C, h->Phi, s);
     if (rc) return rc;
     HIP_TRY(lbm::launch_equilibrium_init(h->cc, h->C, h->Phi, h->f[h->cur], s));
-    HIP_TRY(lbm::launch_moment(h->cc, h->f[h->cur], h->C, s));
+    rc = refresh_C(h, s);
+    if (rc) return rc;
     if (!on_device) HIP_TRY(hipStreamSynchronize(s));  // the host buffer may be reused on return
     h->has_state = true;
     h->at_initial_C = true;
@@ -538,12 +577,8 @@ int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream)
     hipStream_t s = as_stream(stream);
     const int every = h->params.nonfinite_check_every;
     for (int64_t m = 0; m < n; ++m) {
-        rc = run_phi(h, h->C, h->Phi, s);
+        rc = forward_step(h, s);
         if (rc) return rc;
-        HIP_TRY(lbm::launch_collide_stream(h->cc, h->f[h->cur], h->f[1 - h->cur], h->Phi, h->S, h->C, s));
-        h->cur = 1 - h->cur;
-        h->steps_done += 1;
-        h->at_initial_C = false;
         if (every > 0 && h->steps_done % every == 0) {
             int flag = 0;
             HIP_TRY(hipMemsetAsync(h->flag, 0, sizeof(int), s));
@@ -591,7 +626,8 @@ int lbm_fade_set_f(lbm_fade_t h, const float* src, int32_t on_device, void* stre
     if (rc) return rc;
     hipStream_t s = as_stream(stream);
     HIP_TRY(hipMemcpyAsync(h->f[h->cur], src, sizeof(float) * h->Q * h->nodes, kind_to_dev(on_device), s));
-    HIP_TRY(lbm::launch_moment(h->cc, h->f[h->cur], h->C, s));
+    rc = refresh_C(h, s);
+    if (rc) return rc;
     if (!on_device) HIP_TRY(hipStreamSynchronize(s));
     h->has_state = true;
     h->at_initial_C = false;

@@ -22,6 +22,8 @@ struct lbm_fade {
     float* C = nullptr;
     float* Phi = nullptr;
     float* S = nullptr;
+    uint32_t* Cp = nullptr;       // split-BF16 path: packed BF16 split of C, kept in sync with C
+    uint32_t* Cp_tmp = nullptr;   // split-BF16 path: packed split of other inputs of the operator
     void* opmem = nullptr;  // generators, corrections and BF16 splits of all axes
     int* flag = nullptr;
     lbm::AxisOp ops[3];
@@ -48,6 +50,9 @@ struct AxisCoeffs {
 AxisCoeffs axis_coeffs(int n, double gamma, double g, double dx);
 // Fractional term of every axis of C into Phi (d consecutive node fields).
 int fade_run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s);
+// One forward time step of the handle's state (fractional term, then the
+// fused collide-stream kernel, which also refreshes C and its BF16 split).
+int fade_forward_step(lbm_fade* h, hipStream_t s);
 // Adjoint driver (adjoint.hip).
 int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_device, lbm_grads* out,
                 float* dC0, float* dS, hipStream_t s, std::string& msg);

@@ -43,7 +43,8 @@ struct FracLaunch {
     AxisLayout lay[3];
     int tiles_m[3], tiles_n[3];
     int first[4];  // first workgroup id of every axis, first[naxes] = grid size
-    const float* C[3];  // input field of every axis
+    const float* C[3];      // input field of every axis
+    const uint32_t* Cp[3];  // the same fields split into BF16 (hi | lo << 16) (split-BF16 path)
     float* Phi[3];
     int naxes;
 };
@@ -61,11 +62,15 @@ struct CollideConsts {
 
 // Kernel launchers (host functions).  All return a hipError_t.
 // Fractional term of all axes: axis a reads C + a * in_stride (in_stride = 0:
-// one field for every axis) and writes Phi + a * nodes.
+// one field for every axis) and writes Phi + a * nodes.  The split-BF16 path
+// (precision 1) also reads Cp, the same fields packed by launch_pack_bf16.
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
-                             int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s);
+                             const uint32_t* Cp, int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s);
+// Cp[x] = bf16(C[x]) | bf16(C[x] - bf16(C[x])) << 16 (round to nearest even).
+hipError_t launch_pack_bf16(const float* C, uint32_t* Cp, int64_t count, hipStream_t s);
+// C_out receives the new moment; Cp_out (nullable) also its packed BF16 split.
 hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
-                                 const float* S, float* C_out, hipStream_t s);
+                                 const float* S, float* C_out, uint32_t* Cp_out, hipStream_t s);
 hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f,
                                    hipStream_t s);
 hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t s);
