@@ -365,6 +365,362 @@ hipError_t run_bf16(FracLaunch& L, hipStream_t s)
     return go(fractional_bf16x3_mfma<BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1>);
 }
 
+
+// ---------------------------------------------------------------------------
+// Register-ring kernel.  One wavefront computes 32 lines x (32 NBJ) outputs
+// of one axis over its share of k, in steps of 16 k:
+//  * the C fragment of a step (32 lines x 16 k) is loaded straight from the
+//    packed field into registers, P steps ahead (no LDS, no barrier in the
+//    k loop): along the contiguous axis a lane reads 8 consecutive packed
+//    words (two 16-byte loads), along a strided axis 8 words of one line at
+//    successive k, each load coalesced across the lanes (consecutive lines);
+//  * the Toeplitz fragment of output block c at step t equals that of block
+//    0 at step t - 2c (T(j + 32c - k) = T(j - (k - 32c))), so only the
+//    block-0 fragment of each new step is read; the last 2 NBJ of them stay
+//    in a register ring indexed by the step modulo 2 NBJ (the k loop is
+//    unrolled by that period so every ring index is static);
+//  * Toeplitz fragments are read from an LDS window of pair words
+//    W(d) = T(d) | T(d - 1) << 16 (hi and lo planes) stored with d
+//    decreasing: the 8 values of a lane, T(d0), T(d0 - 1), ..., T(d0 - 7),
+//    are the four words W(d0), W(d0 - 2), W(d0 - 4), W(d0 - 6) at increasing
+//    addresses (two ds_read2), already in MFMA operand order.
+// A workgroup has 4 wavefronts: WL line blocks x KSPLIT k-shares; k-shares
+// are summed through LDS in a fixed order (deterministic).
+template <bool CONTIG, int NBJ, int WL, int KSPLIT, int P, bool VEC, bool KFULL>
+__device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLayout& lay, const float* __restrict__ C,
+                                                 const uint32_t* __restrict__ Cp, float* __restrict__ Phi,
+                                                 int tiles_l, int tiles_j, int bid, int total, unsigned char* smem)
+{
+    static_assert(WL * KSPLIT == kWaves, "4 wavefronts per workgroup");
+    constexpr int R = 2 * NBJ;  // Toeplitz ring period (steps)
+    static_assert(R % P == 0, "prefetch depth divides the ring period");
+    constexpr int JT = 32 * NBJ;  // outputs per tile
+    const int n = op.n, N = n - 1;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: keeps the k loop scalar
+    const int wl = wave / KSPLIT, wk = wave % KSPLIT;
+    const int li = lane & 31, lh = lane >> 5;
+
+    int lin = bid;
+    if ((total & 7) == 0) lin = (bid & 7) * (total >> 3) + (bid >> 3);  // consecutive tiles on one XCD
+    const int jt = lin % tiles_j;
+    const int rest = lin / tiles_j;
+    const int lt = rest % tiles_l;
+    const int batch = rest / tiles_l;
+    const int j0 = jt * JT;
+    const int64_t lines = lay.lines;
+    const int64_t line0 = (int64_t)lt * (32 * WL) + 32 * wl;
+    const int64_t js = lay.j_stride;
+    const float* Cb = C;
+    const uint32_t* Cpb = Cp;
+    float* Pb = Phi;
+    if (!CONTIG) {
+        Cb += (int64_t)batch * lay.batch_stride;
+        Cpb += (int64_t)batch * lay.batch_stride;
+        Pb += (int64_t)batch * lay.batch_stride;
+    }
+
+    // k range of the tile (one-sided operators skip the zero triangle)
+    int kb = 0, ke = n;
+    if (op.lower_only) ke = min(n, j0 + JT);
+    if (op.upper_only) kb = (min(j0, n - 1) / 16) * 16;
+    const int steps = (ke - kb + 15) / 16;
+    const int kend = kb + 16 * steps;
+    const int spw = (steps + KSPLIT - 1) / KSPLIT;
+    const int t_first = wk * spw;
+    const int my_steps = max(0, min(steps, t_first + spw) - t_first);
+
+    // LDS: corr0 | corrN | (pair-word window hi | lo, later the k-share reduction)
+    float* c0s = reinterpret_cast<float*>(smem);
+    float* cNs = c0s + JT;
+    uint32_t* pwh = reinterpret_cast<uint32_t*>(cNs + JT);
+    const int dmin = j0 - kend + 1;
+    const int wlen = JT - 1 + (kend - kb);  // d in [dmin, dmax], word m holds d = dmax - m
+    const int dmax = dmin + wlen - 1;
+    uint32_t* pwl = pwh + wlen;
+    for (int t = threadIdx.x; t < JT; t += kThreads) {
+        const int j = j0 + t;
+        c0s[t] = j < n ? op.corr0[j] : 0.f;
+        cNs[t] = j < n ? op.corrN[j] : 0.f;
+    }
+    for (int i = threadIdx.x; i < wlen; i += kThreads) {
+        const int d = dmax - i;
+        const uint32_t g1 = (d >= -N && d <= N) ? ((uint32_t)op.gen_hi[d + N] | ((uint32_t)op.gen_lo[d + N] << 16)) : 0u;
+        const int e = d - 1;
+        const uint32_t g0 = (e >= -N && e <= N) ? ((uint32_t)op.gen_hi[e + N] | ((uint32_t)op.gen_lo[e + N] << 16)) : 0u;
+        pwh[i] = __builtin_amdgcn_perm(g0, g1, 0x05040100u);  // hi(d) | hi(d - 1) << 16
+        pwl[i] = __builtin_amdgcn_perm(g0, g1, 0x07060302u);  // lo(d) | lo(d - 1) << 16
+    }
+    __syncthreads();
+
+    f32x16 acc[NBJ];
+#pragma unroll
+    for (int c = 0; c < NBJ; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+
+    if (my_steps > 0) {
+        const int kw = kb + 16 * t_first;  // first k of this wavefront
+        // C fragment addresses: lane = (line li, k group lh).  Steps past the
+        // end of the range re-read the last step (their values are unused),
+        // so every step issues the same loads.
+        const int64_t my_line = min(line0 + li, lines - 1);  // rows past the end are computed, never stored
+        const uint32_t* q = CONTIG ? Cpb + my_line * n + kw + 8 * lh : Cpb + (int64_t)(kw + 8 * lh) * js + my_line;
+        auto load_raw = [&](int t, uint32_t (&w)[8]) {
+            const int tc = min(t, my_steps - 1);
+            if constexpr (KFULL) {
+                // every k of every step is < n: no guards, no branches
+                if constexpr (CONTIG) {
+                    const u32x4 v0 = *reinterpret_cast<const u32x4*>(q + 16 * tc);
+                    const u32x4 v1 = *reinterpret_cast<const u32x4*>(q + 16 * tc + 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        w[e] = v0[e];
+                        w[4 + e] = v1[e];
+                    }
+                } else {
+                    const uint32_t* a = q + (int64_t)(16 * tc) * js;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) w[e] = a[(int64_t)e * js];
+                }
+            } else {
+                // the last step may pass the end of the axis: values there are 0
+                const int k = kw + 16 * tc + 8 * lh;  // first k of this lane
+                if constexpr (CONTIG && VEC) {
+                    const bool ok = k < n;  // n % 8 == 0: all 8 values in range, or none
+                    const uint32_t* a = ok ? q + 16 * tc : Cpb;
+                    const u32x4 v0 = *reinterpret_cast<const u32x4*>(a);
+                    const u32x4 v1 = *reinterpret_cast<const u32x4*>(a + 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        w[e] = ok ? v0[e] : 0u;
+                        w[4 + e] = ok ? v1[e] : 0u;
+                    }
+                } else {
+                    const int64_t stride = CONTIG ? 1 : js;
+                    const uint32_t* a = q + (int64_t)(16 * tc) * stride;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const bool ok = k + e < n;
+                        const uint32_t v = *(ok ? a + e * stride : Cpb);
+                        w[e] = ok ? v : 0u;
+                    }
+                }
+            }
+        };
+        auto cvt = [&](const uint32_t (&w)[8], bf16x8& hi, bf16x8& lo) {
+            u32x4 h, l;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                h[p] = __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x05040100u);
+                l[p] = __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x07060302u);
+            }
+            hi = __builtin_bit_cast(bf16x8, h);
+            lo = __builtin_bit_cast(bf16x8, l);
+        };
+        // block-0 Toeplitz fragment of step t: lane = (output j0 + li, k group lh)
+        const int mbase = dmax - (j0 + li - 8 * lh - kw);  // window word of d0 at t = 0
+        auto load_t = [&](int t, bf16x8& hi, bf16x8& lo) {
+            const int m0 = min(mbase + 16 * t, wlen - 7);  // steps past the end read a clamped (unused) fragment
+            u32x4 h, l;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                h[p] = pwh[m0 + 2 * p];
+                l[p] = pwl[m0 + 2 * p];
+            }
+            hi = __builtin_bit_cast(bf16x8, h);
+            lo = __builtin_bit_cast(bf16x8, l);
+        };
+
+        uint32_t raw[P][8];
+        bf16x8 th[R], tl[R];
+        bf16x8 ch[2], cl[2];
+#pragma unroll
+        for (int q = 0; q < P; ++q) load_raw(q, raw[q]);
+        // ring slots of steps -R+2 .. 0 (blocks c >= 1 of the first steps)
+#pragma unroll
+        for (int t = -(R - 2); t <= 0; ++t) load_t(t, th[(t + R) % R], tl[(t + R) % R]);
+        cvt(raw[0], ch[0], cl[0]);
+
+        for (int t0 = 0; t0 < my_steps; t0 += R) {
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int t = t0 + u;
+                // prefetch: Toeplitz fragment of step t + 1, C of step t + P (slot of step t, converted already)
+                load_t(t + 1, th[(u + 1) % R], tl[(u + 1) % R]);
+                load_raw(t + P, raw[u % P]);
+                cvt(raw[(u + 1) % P], ch[(u + 1) & 1], cl[(u + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (t < my_steps) {
+                    const bf16x8 chh = ch[u & 1], cll = cl[u & 1];
+#pragma unroll
+                    for (int term = 0; term < 3; ++term)
+#pragma unroll
+                        for (int c = 0; c < NBJ; ++c) {
+                            const int slot = ((u - 2 * c) % R + R) % R;
+                            const bf16x8 tt = term == 1 ? tl[slot] : th[slot];
+                            const bf16x8 cc = term == 0 ? cll : chh;
+                            if constexpr (CONTIG)
+                                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cc, tt, acc[c], 0, 0, 0);
+                            else
+                                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tt, cc, acc[c], 0, 0, 0);
+                        }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    int c_lo = 0, c_hi = NBJ;
+    if constexpr (KSPLIT > 1) {
+        __syncthreads();  // every wavefront is done with the pair-word window
+        float* red = reinterpret_cast<float*>(pwh);
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                float4 v = make_float4(acc[c][4 * r4], acc[c][4 * r4 + 1], acc[c][4 * r4 + 2], acc[c][4 * r4 + 3]);
+                *reinterpret_cast<float4*>(red + (((wave * NBJ + c) * 4 + r4) * 64 + lane) * 4) = v;
+            }
+        __syncthreads();
+        c_lo = wk * (NBJ / KSPLIT);
+        c_hi = c_lo + NBJ / KSPLIT;
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c) {
+            if (c < c_lo || c >= c_hi) continue;
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int s = 0; s < KSPLIT; ++s) {
+                    const float4 v =
+                        *reinterpret_cast<const float4*>(red + ((((wl * KSPLIT + s) * NBJ + c) * 4 + r4) * 64 + lane) * 4);
+                    sum.x += v.x;
+                    sum.y += v.y;
+                    sum.z += v.z;
+                    sum.w += v.w;
+                }
+                acc[c][4 * r4] = sum.x;
+                acc[c][4 * r4 + 1] = sum.y;
+                acc[c][4 * r4 + 2] = sum.z;
+                acc[c][4 * r4 + 3] = sum.w;
+            }
+        }
+    }
+
+    // epilogue: boundary columns (rank-2 correction) and stores
+    if constexpr (CONTIG) {
+        // rows = lines (8 (r / 4) + 4 lh + r % 4), columns = outputs j0 + 32 c + li
+        float cb0[16], cbN[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t line = min(line0 + 8 * (r >> 2) + 4 * lh + (r & 3), lines - 1);
+            cb0[r] = Cb[line * n];
+            cbN[r] = Cb[line * n + N];
+        }
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c) {
+            if (c < c_lo || c >= c_hi) continue;
+            const int jl = 32 * c + li, j = j0 + jl;
+            const float k0 = c0s[jl], kN = cNs[jl];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t line = line0 + 8 * (r >> 2) + 4 * lh + (r & 3);
+                if (line < lines && j < n) {
+                    float v = acc[c][r];
+                    v = fmaf(k0, cb0[r], v);
+                    v = fmaf(kN, cbN[r], v);
+                    Pb[line * n + j] = v;
+                }
+            }
+        }
+    } else {
+        // rows = outputs j0 + 32 c + 8 (r / 4) + 4 lh + r % 4, columns = lines line0 + li
+        const int64_t line = line0 + li;
+        const int64_t lc = min(line, lines - 1);
+        const float b0 = Cb[lc], bN = Cb[(int64_t)N * js + lc];
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c) {
+            if (c < c_lo || c >= c_hi) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int jl = 32 * c + 8 * (r >> 2) + 4 * lh + (r & 3), j = j0 + jl;
+                if (line < lines && j < n) {
+                    float v = acc[c][r];
+                    v = fmaf(c0s[jl], b0, v);
+                    v = fmaf(cNs[jl], bN, v);
+                    Pb[(int64_t)j * js + line] = v;
+                }
+            }
+        }
+    }
+}
+
+template <int NBJ, int WL, int KSPLIT, int P, bool VEC_X, bool KFULL>
+__global__ __launch_bounds__(kThreads) void fractional_bf16x3_ring(FracLaunch L)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_r[];
+    const int bid = blockIdx.x;
+    int axis = 0;
+    while (axis + 1 < L.naxes && bid >= L.first[axis + 1]) ++axis;
+    const int local = bid - L.first[axis];
+    const int total = L.first[axis + 1] - L.first[axis];
+    if (axis == 0)
+        bf16x3_ring_tile<true, NBJ, WL, KSPLIT, P, VEC_X, KFULL>(L.op[0], L.lay[0], L.C[0], L.Cp[0], L.Phi[0], L.tiles_m[0],
+                                                          L.tiles_n[0], local, total, smem_r);
+    else
+        bf16x3_ring_tile<false, NBJ, WL, KSPLIT, P, false, KFULL>(L.op[axis], L.lay[axis], L.C[axis], L.Cp[axis],
+                                                           L.Phi[axis], L.tiles_m[axis], L.tiles_n[axis], local, total,
+                                                           smem_r);
+}
+
+// tiles_m = line tiles (32 WL lines), tiles_n = output tiles (32 NBJ outputs)
+template <int NBJ, int WL, int KSPLIT>
+void ring_grid(FracLaunch& L, int64_t& grid, size_t& lds)
+{
+    grid = 0;
+    lds = 0;
+    for (int a = 0; a < L.naxes; ++a) {
+        const AxisOp& op = L.op[a];
+        const AxisLayout& lay = L.lay[a];
+        L.tiles_m[a] = (int)((lay.lines + 32 * WL - 1) / (32 * WL));
+        L.tiles_n[a] = (op.n + 32 * NBJ - 1) / (32 * NBJ);
+        L.first[a] = (int)grid;
+        grid += (int64_t)L.tiles_m[a] * L.tiles_n[a] * (lay.contiguous ? 1 : lay.batches);
+        const size_t kspan = (size_t)((op.n + 15) / 16) * 16;
+        size_t window = sizeof(uint32_t) * 2 * (32 * NBJ - 1 + kspan);
+        const size_t red = KSPLIT > 1 ? sizeof(float) * kWaves * NBJ * 16 * 64 : 0;
+        window = window > red ? window : red;
+        const size_t need = sizeof(float) * 2 * 32 * NBJ + window;
+        lds = need > lds ? need : lds;
+    }
+}
+
+template <int NBJ, int WL, int KSPLIT, int P>
+hipError_t run_ring(FracLaunch& L, hipStream_t s)
+{
+    int64_t grid = 0;
+    size_t lds = 0;
+    ring_grid<NBJ, WL, KSPLIT>(L, grid, lds);
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    L.first[L.naxes] = (int)grid;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    auto go = [&](auto kern) -> hipError_t {
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), lds, s, L);
+        return hipGetLastError();
+    };
+    bool kfull = true;  // every axis a multiple of 16: no step passes the end of an axis
+    for (int a = 0; a < L.naxes; ++a) kfull = kfull && (L.op[a].n % 16) == 0;
+    if (kfull) return go(fractional_bf16x3_ring<NBJ, WL, KSPLIT, P, true, true>);
+    if (L.op[0].n % 8 == 0) return go(fractional_bf16x3_ring<NBJ, WL, KSPLIT, P, true, false>);
+    return go(fractional_bf16x3_ring<NBJ, WL, KSPLIT, P, false, false>);
+}
+
 }  // namespace
 
 bool have_bf16x3() { return true; }
@@ -379,10 +735,23 @@ hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s)
     case 4: return run_bf16<64, 128, 64, 1, 2, 2>(L, s);
     case 5: return run_bf16<128, 128, 32, 2, 2, 1>(L, s);
     case 6: return run_bf16<128, 128, 64, 2, 2, 1>(L, s);
+    case 7: return run_ring<8, 1, 4, 4>(L, s);
+    case 8: return run_ring<8, 2, 2, 4>(L, s);
+    case 9: return run_ring<8, 4, 1, 4>(L, s);
     default: break;
     }
-    if (big_tiles(L) < 512) return run_bf16<64, 64, 128, 1, 1, 4>(L, s);
-    return run_bf16<128, 128, 32, 2, 2, 1>(L, s);
+    // Register-ring kernel; the k loop is split across the wavefronts of a
+    // workgroup when there are too few (32 x 256)-output tiles to fill the chip.
+    {
+        FracLaunch T = L;
+        int64_t grid = 0;
+        size_t lds = 0;
+        ring_grid<8, 4, 1>(T, grid, lds);
+        if (grid >= 512) return run_ring<8, 4, 1, 4>(L, s);
+        ring_grid<8, 2, 2>(T, grid, lds);
+        if (grid >= 256) return run_ring<8, 2, 2, 4>(L, s);
+        return run_ring<8, 1, 4, 4>(L, s);
+    }
 }
 
 }  // namespace lbm

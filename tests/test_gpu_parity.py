@@ -90,6 +90,32 @@ def test_fractional_term_bf16x3_matches_oracle(case):
     assert err < 2e-5
 
 
+TILE_CASES = [
+    (2, [256, 96], [1.3, 1.7], [0.3, 0.8]),    # every axis a multiple of 16
+    (2, [130, 97], [1.5, 1.2], [1.0, 0.0]),    # ragged, one-sided operators
+    (3, [48, 33, 32], [1.5, 1.6, 1.8], [0.5, 0.2, 0.9]),
+]
+
+
+@pytest.mark.parametrize("choice", [f"fp32:{c}" for c in range(1, 7)] + [f"bf16x3:{c}" for c in range(1, 10)])
+@pytest.mark.parametrize("case", TILE_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
+def test_every_tile_configuration(case, choice, monkeypatch):
+    """Each explicitly selectable GEMM configuration (LBM_FP32_TILE / LBM_BF16_TILE)
+    against the oracle, with the bounds of the default path."""
+    precision, c = choice.split(":")
+    dim, n, alpha, p = case
+    _banner(f"phi {precision} tile {c} dim={dim} n={n}")
+    monkeypatch.setenv("LBM_FP32_TILE" if precision == "fp32" else "LBM_BF16_TILE", c)
+    cfg = synth.small(dim, n, alpha=alpha, p=p, seed=33)
+    rng = np.random.default_rng(19)
+    C = rng.uniform(0.0, 1.0, synth.shape(cfg)).astype(np.float32)
+    ref = oracle.phi(cfg, C.astype(np.float64))
+    with _solver(cfg, precision) as s:
+        got = s.apply_phi(torch.from_numpy(C).cuda()).cpu().numpy().astype(np.float64)
+    rel = 4 * max(n) * 2.0**-24 if precision == "fp32" else 2.0**-14
+    assert np.all(np.abs(got - ref) <= rel * np.abs(ref) + 1e-30), np.max(np.abs(got - ref) / np.abs(ref))
+
+
 def test_bf16x3_split_is_not_plain_bf16():
     """The 3-term split must be far more accurate than a single BF16 rounding
     (2^-9 relative): guards against a silently dropped correction term."""
