@@ -81,18 +81,19 @@ def time_steps(torch, solver, steps: int) -> float:
     return start.elapsed_time(end) / 1e3
 
 
-def time_gemm(torch, solver, C_dev, reps: int) -> float:
-    """Average seconds of the fractional-term launches of one step (all axes),
-    timed by HIP events on the stream they are launched on."""
+def time_gemm(torch, solver, reps: int) -> float:
+    """Average seconds of the fractional-term launch of one step (one kernel,
+    all axes, on the solver's current C exactly as inside a step), timed by
+    HIP events on the stream it is launched on."""
     out = torch.empty((solver.dim,) + solver.shape, dtype=torch.float32, device="cuda")
     for _ in range(3):
-        solver.apply_phi(C_dev, out=out)
+        solver.apply_phi(None, out=out)
     stream = torch.cuda.current_stream()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
     for _ in range(reps):
-        solver.apply_phi(C_dev, out=out)
+        solver.apply_phi(None, out=out)
     end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end) / 1e3 / reps
@@ -183,7 +184,7 @@ def main():
             s.step(args.warmup)
             secs = time_steps(torch, s, args.steps)
             log(f"{precision}: {args.steps} steps in {secs * 1e3:.2f} ms")
-            gemm_s = time_gemm(torch, s, s.get_C(), reps=max(20, min(500, args.steps)))
+            gemm_s = time_gemm(torch, s, reps=max(20, min(500, args.steps)))
             err = None
             if not args.no_accuracy:
                 s.set_C(C0)

@@ -132,6 +132,9 @@ LBM_API int lbm_fade_set_f(lbm_fade_t h, const float* src, int32_t on_device, vo
 /* Apply the fractional operator of Sec. 2.4 to a given field:
  * Phi[mu*nodes + node] = p_mu I+(g_mu C) + (1-p_mu) I-(g_mu C) for every axis,
  * with the handle's precision.  C and Phi are host or device (same on_device).
+ * C = NULL applies it to the solver's current concentration (device Phi only;
+ * LBM_ESTATE before set_C/set_f): in split-BF16 mode this reuses the split the
+ * last step produced, so the call is exactly the GEMM launch of a step.
  * Does not touch the solver state. */
 LBM_API int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t on_device, void* stream);
 

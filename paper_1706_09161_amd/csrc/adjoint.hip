@@ -370,6 +370,7 @@ bool build_ops(lbm_fade* h, AdjointState* A)
         T.corr0 = reinterpret_cast<const float*>(base + oT0);  // zeros
         T.corrN = reinterpret_cast<const float*>(base + oTN);  // zeros
         T.gen_hi = T.gen_lo = nullptr;
+        T.pw_hi = T.pw_lo = nullptr;
         AxisOp& P = A->opsP[mu];
         P.n = n;
         P.lower_only = P.upper_only = 0;
@@ -377,6 +378,7 @@ bool build_ops(lbm_fade* h, AdjointState* A)
         P.corr0 = reinterpret_cast<const float*>(base + oP0);
         P.corrN = reinterpret_cast<const float*>(base + oPN);
         P.gen_hi = P.gen_lo = nullptr;
+        P.pw_hi = P.pw_lo = nullptr;
     }
     return hipMemcpy(A->opmem, host.data(), bytes, hipMemcpyHostToDevice) == hipSuccess;
 }

@@ -488,11 +488,11 @@ int64_t big_tiles(const FracLaunch& L)
 
 int tile_choice(const char* var)
 {
-    // 0 = automatic; 1..9 = the explicit configurations listed at the call sites
+    // 0 = automatic; 1..12 = the explicit configurations listed at the call sites
     const char* v = getenv(var);
     if (!v || !*v) return 0;
     const int c = atoi(v);
-    return (c >= 1 && c <= 9) ? c : 0;
+    return (c >= 1 && c <= 12) ? c : 0;
 }
 
 }  // namespace lbm

@@ -395,21 +395,36 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     constexpr int R = 2 * NBJ;  // Toeplitz ring period (steps)
     static_assert(R % P == 0, "prefetch depth divides the ring period");
     constexpr int JT = 32 * NBJ;  // outputs per tile
+    static_assert(JT <= kThreads && JT <= 512, "one thread per output of the tile; pair-word arrays sized for 512");
+    constexpr int LT = 32 * WL;  // lines per tile
     const int n = op.n, N = n - 1;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: keeps the k loop scalar
     const int wl = wave / KSPLIT, wk = wave % KSPLIT;
     const int li = lane & 31, lh = lane >> 5;
 
+    // Tile of this workgroup.  Workgroups are dealt to the 8 XCDs round robin;
+    // each XCD gets a contiguous range of tiles (the output tiles of a few line
+    // blocks, which share C in its L2).  One-sided operators make the k range
+    // grow (p = 1) or shrink (p = 0) with the output tile: there each XCD
+    // starts its longest tiles first.
     int lin = bid;
-    if ((total & 7) == 0) lin = (bid & 7) * (total >> 3) + (bid >> 3);  // consecutive tiles on one XCD
-    const int jt = lin % tiles_j;
+    if ((total & 7) == 0) {
+        const int S = total >> 3, x = bid & 7, i = bid >> 3;
+        lin = x * S + i;
+        if ((op.lower_only || op.upper_only) && S % tiles_j == 0) {
+            const int lpx = S / tiles_j;  // line blocks per XCD
+            lin = x * S + (i % lpx) * tiles_j + i / lpx;
+        }
+    }
+    int jt = lin % tiles_j;
+    if (op.lower_only) jt = tiles_j - 1 - jt;
     const int rest = lin / tiles_j;
     const int lt = rest % tiles_l;
     const int batch = rest / tiles_l;
     const int j0 = jt * JT;
     const int64_t lines = lay.lines;
-    const int64_t line0 = (int64_t)lt * (32 * WL) + 32 * wl;
+    const int64_t line0 = (int64_t)lt * LT + 32 * wl;
     const int64_t js = lay.j_stride;
     const float* Cb = C;
     const uint32_t* Cpb = Cp;
@@ -424,32 +439,150 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     int kb = 0, ke = n;
     if (op.lower_only) ke = min(n, j0 + JT);
     if (op.upper_only) kb = (min(j0, n - 1) / 16) * 16;
-    const int steps = (ke - kb + 15) / 16;
+    const int steps = (ke - kb + 15) / 16;  // >= 1
     const int kend = kb + 16 * steps;
     const int spw = (steps + KSPLIT - 1) / KSPLIT;
     const int t_first = wk * spw;
     const int my_steps = max(0, min(steps, t_first + spw) - t_first);
+    const int kw = kb + 16 * min(t_first, steps - 1);  // first k of this wavefront (clamped when it has none)
+    const int last = max(my_steps, 1) - 1;             // last step whose C is read
 
-    // LDS: corr0 | corrN | (pair-word window hi | lo, later the k-share reduction)
+    // ---- C fragments: lane = (line li, k group lh).  Steps past the end of
+    // the range re-read the last step, so every step issues the same loads.
+    const int64_t my_line = min(line0 + li, lines - 1);  // rows past the end are computed, never stored
+    const uint32_t* q = CONTIG ? Cpb + my_line * n + kw + 8 * lh : Cpb + (int64_t)(kw + 8 * lh) * js + my_line;
+    auto load_raw = [&](int t, uint32_t (&w)[8]) {
+        const int tc = min(t, last);
+        if constexpr (KFULL) {
+            // every k of every step is < n: no guards, no branches
+            if constexpr (CONTIG) {
+                const u32x4 v0 = *reinterpret_cast<const u32x4*>(q + 16 * tc);
+                const u32x4 v1 = *reinterpret_cast<const u32x4*>(q + 16 * tc + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    w[e] = v0[e];
+                    w[4 + e] = v1[e];
+                }
+            } else {
+                const uint32_t* a = q + (int64_t)(16 * tc) * js;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) w[e] = a[(int64_t)e * js];
+            }
+        } else {
+            // the last step may pass the end of the axis: values there are 0
+            const int k = kw + 16 * tc + 8 * lh;  // first k of this lane
+            if constexpr (CONTIG && VEC) {
+                const bool ok = k < n;  // n % 8 == 0: all 8 values in range, or none
+                const uint32_t* a = ok ? q + 16 * tc : Cpb;
+                const u32x4 v0 = *reinterpret_cast<const u32x4*>(a);
+                const u32x4 v1 = *reinterpret_cast<const u32x4*>(a + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    w[e] = ok ? v0[e] : 0u;
+                    w[4 + e] = ok ? v1[e] : 0u;
+                }
+            } else {
+                const int64_t stride = CONTIG ? 1 : js;
+                const uint32_t* a = q + (int64_t)(16 * tc) * stride;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const bool ok = k + e < n;
+                    const uint32_t v = *(ok ? a + e * stride : Cpb);
+                    w[e] = ok ? v : 0u;
+                }
+            }
+        }
+    };
+    // BF16 hi and lo planes of a C fragment; zero for steps past the end of
+    // this wavefront's range (their products then add nothing, so every step
+    // runs the same straight-line code)
+    auto cvt = [&](const uint32_t (&w)[8], bool live, bf16x8& hi, bf16x8& lo) {
+        u32x4 h, l;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            h[p] = live ? __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x05040100u) : 0u;
+            l[p] = live ? __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x07060302u) : 0u;
+        }
+        hi = __builtin_bit_cast(bf16x8, h);
+        lo = __builtin_bit_cast(bf16x8, l);
+    };
+    // ---- LDS: corr0 | corrN | C at the two walls of each line (contiguous
+    // axis) | pair-word window hi | lo (later the k-share reduction)
     float* c0s = reinterpret_cast<float*>(smem);
     float* cNs = c0s + JT;
-    uint32_t* pwh = reinterpret_cast<uint32_t*>(cNs + JT);
-    const int dmin = j0 - kend + 1;
-    const int wlen = JT - 1 + (kend - kb);  // d in [dmin, dmax], word m holds d = dmax - m
-    const int dmax = dmin + wlen - 1;
-    uint32_t* pwl = pwh + wlen;
-    for (int t = threadIdx.x; t < JT; t += kThreads) {
-        const int j = j0 + t;
-        c0s[t] = j < n ? op.corr0[j] : 0.f;
-        cNs[t] = j < n ? op.corrN[j] : 0.f;
+    float* w0s = cNs + JT;
+    float* wNs = w0s + LT;
+    uint32_t* pwh = reinterpret_cast<uint32_t*>(wNs + LT);
+    const int wlen = JT - 1 + (kend - kb);  // d in [dmax - wlen + 1, dmax], word m holds d = dmax - m
+    const int wpad = (wlen + 3) & ~3;
+    const int dmax = j0 + JT - 1 - kb;      // = 15 (mod 16), so the copy below starts 64-byte aligned
+    uint32_t* pwl = pwh + wpad;
+    const int nq = wpad / 4;                // 16-byte words per plane
+    const int x0 = op.pw_top - dmax;
+    constexpr int FU = 8;                   // 16-byte words per thread and round of the copy
+    auto fill_load = [&](int base, u32x4 (&v)[FU]) {
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int idx = base + u * kThreads + threadIdx.x;
+            if (idx < 2 * nq) {
+                const bool lo = idx >= nq;
+                const int qq = lo ? idx - nq : idx;
+                v[u] = *reinterpret_cast<const u32x4*>((lo ? op.pw_lo : op.pw_hi) + x0 + 4 * qq);
+            }
+        }
+    };
+    auto fill_store = [&](int base, const u32x4 (&v)[FU]) {
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int idx = base + u * kThreads + threadIdx.x;
+            if (idx < 2 * nq) {
+                const bool lo = idx >= nq;
+                const int qq = lo ? idx - nq : idx;
+                *reinterpret_cast<u32x4*>((lo ? pwl : pwh) + 4 * qq) = v[u];
+            }
+        }
+    };
+    // Loads complete in issue order, so the set-up loads go first, then the
+    // first P steps of C (their latency overlaps the set-up), then the stores.
+    u32x4 fv[FU];
+    fill_load(0, fv);
+    float cv0 = 0.f, cvN = 0.f, wv0 = 0.f, wvN = 0.f;
+    {
+        const int t = threadIdx.x;  // JT <= kThreads
+        if (t < JT && j0 + t < n) {
+            cv0 = op.corr0[j0 + t];
+            cvN = op.corrN[j0 + t];
+        }
+        if (CONTIG && t < LT) {
+            const int64_t line = min((int64_t)lt * LT + t, lines - 1);
+            wv0 = Cb[line * n];
+            wvN = Cb[line * n + N];
+        }
     }
-    for (int i = threadIdx.x; i < wlen; i += kThreads) {
-        const int d = dmax - i;
-        const uint32_t g1 = (d >= -N && d <= N) ? ((uint32_t)op.gen_hi[d + N] | ((uint32_t)op.gen_lo[d + N] << 16)) : 0u;
-        const int e = d - 1;
-        const uint32_t g0 = (e >= -N && e <= N) ? ((uint32_t)op.gen_hi[e + N] | ((uint32_t)op.gen_lo[e + N] << 16)) : 0u;
-        pwh[i] = __builtin_amdgcn_perm(g0, g1, 0x05040100u);  // hi(d) | hi(d - 1) << 16
-        pwl[i] = __builtin_amdgcn_perm(g0, g1, 0x07060302u);  // lo(d) | lo(d - 1) << 16
+    // strided axes: the wall values of this lane's line
+    float b0 = 0.f, bN = 0.f;
+    if constexpr (!CONTIG) {
+        b0 = Cb[my_line];
+        bN = Cb[(int64_t)N * js + my_line];
+    }
+    uint32_t raw[P][8];
+#pragma unroll
+    for (int t = 0; t < P; ++t) load_raw(t, raw[t]);
+    fill_store(0, fv);
+    {
+        const int t = threadIdx.x;
+        if (t < JT) {
+            c0s[t] = cv0;
+            cNs[t] = cvN;
+        }
+        if (CONTIG && t < LT) {
+            w0s[t] = wv0;
+            wNs[t] = wvN;
+        }
+    }
+    for (int base = FU * kThreads; base < 2 * nq; base += FU * kThreads) {  // long axes only
+        fill_load(base, fv);
+        fill_store(base, fv);
     }
     __syncthreads();
 
@@ -460,64 +593,6 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
         for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
 
     if (my_steps > 0) {
-        const int kw = kb + 16 * t_first;  // first k of this wavefront
-        // C fragment addresses: lane = (line li, k group lh).  Steps past the
-        // end of the range re-read the last step (their values are unused),
-        // so every step issues the same loads.
-        const int64_t my_line = min(line0 + li, lines - 1);  // rows past the end are computed, never stored
-        const uint32_t* q = CONTIG ? Cpb + my_line * n + kw + 8 * lh : Cpb + (int64_t)(kw + 8 * lh) * js + my_line;
-        auto load_raw = [&](int t, uint32_t (&w)[8]) {
-            const int tc = min(t, my_steps - 1);
-            if constexpr (KFULL) {
-                // every k of every step is < n: no guards, no branches
-                if constexpr (CONTIG) {
-                    const u32x4 v0 = *reinterpret_cast<const u32x4*>(q + 16 * tc);
-                    const u32x4 v1 = *reinterpret_cast<const u32x4*>(q + 16 * tc + 4);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        w[e] = v0[e];
-                        w[4 + e] = v1[e];
-                    }
-                } else {
-                    const uint32_t* a = q + (int64_t)(16 * tc) * js;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) w[e] = a[(int64_t)e * js];
-                }
-            } else {
-                // the last step may pass the end of the axis: values there are 0
-                const int k = kw + 16 * tc + 8 * lh;  // first k of this lane
-                if constexpr (CONTIG && VEC) {
-                    const bool ok = k < n;  // n % 8 == 0: all 8 values in range, or none
-                    const uint32_t* a = ok ? q + 16 * tc : Cpb;
-                    const u32x4 v0 = *reinterpret_cast<const u32x4*>(a);
-                    const u32x4 v1 = *reinterpret_cast<const u32x4*>(a + 4);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        w[e] = ok ? v0[e] : 0u;
-                        w[4 + e] = ok ? v1[e] : 0u;
-                    }
-                } else {
-                    const int64_t stride = CONTIG ? 1 : js;
-                    const uint32_t* a = q + (int64_t)(16 * tc) * stride;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const bool ok = k + e < n;
-                        const uint32_t v = *(ok ? a + e * stride : Cpb);
-                        w[e] = ok ? v : 0u;
-                    }
-                }
-            }
-        };
-        auto cvt = [&](const uint32_t (&w)[8], bf16x8& hi, bf16x8& lo) {
-            u32x4 h, l;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                h[p] = __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x05040100u);
-                l[p] = __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x07060302u);
-            }
-            hi = __builtin_bit_cast(bf16x8, h);
-            lo = __builtin_bit_cast(bf16x8, l);
-        };
         // block-0 Toeplitz fragment of step t: lane = (output j0 + li, k group lh)
         const int mbase = dmax - (j0 + li - 8 * lh - kw);  // window word of d0 at t = 0
         auto load_t = [&](int t, bf16x8& hi, bf16x8& lo) {
@@ -532,15 +607,12 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
             lo = __builtin_bit_cast(bf16x8, l);
         };
 
-        uint32_t raw[P][8];
         bf16x8 th[R], tl[R];
         bf16x8 ch[2], cl[2];
-#pragma unroll
-        for (int q = 0; q < P; ++q) load_raw(q, raw[q]);
         // ring slots of steps -R+2 .. 0 (blocks c >= 1 of the first steps)
 #pragma unroll
         for (int t = -(R - 2); t <= 0; ++t) load_t(t, th[(t + R) % R], tl[(t + R) % R]);
-        cvt(raw[0], ch[0], cl[0]);
+        cvt(raw[0], true, ch[0], cl[0]);
 
         for (int t0 = 0; t0 < my_steps; t0 += R) {
 #pragma unroll
@@ -549,22 +621,29 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
                 // prefetch: Toeplitz fragment of step t + 1, C of step t + P (slot of step t, converted already)
                 load_t(t + 1, th[(u + 1) % R], tl[(u + 1) % R]);
                 load_raw(t + P, raw[u % P]);
-                cvt(raw[(u + 1) % P], ch[(u + 1) & 1], cl[(u + 1) & 1]);
-                __builtin_amdgcn_sched_barrier(0);
-                if (t < my_steps) {
-                    const bf16x8 chh = ch[u & 1], cll = cl[u & 1];
+                cvt(raw[(u + 1) % P], t + 1 < my_steps, ch[(u + 1) & 1], cl[(u + 1) & 1]);
+                const bf16x8 chh = ch[u & 1], cll = cl[u & 1];
 #pragma unroll
-                    for (int term = 0; term < 3; ++term)
+                for (int term = 0; term < 3; ++term)
 #pragma unroll
-                        for (int c = 0; c < NBJ; ++c) {
-                            const int slot = ((u - 2 * c) % R + R) % R;
-                            const bf16x8 tt = term == 1 ? tl[slot] : th[slot];
-                            const bf16x8 cc = term == 0 ? cll : chh;
-                            if constexpr (CONTIG)
-                                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cc, tt, acc[c], 0, 0, 0);
-                            else
-                                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tt, cc, acc[c], 0, 0, 0);
-                        }
+                    for (int c = 0; c < NBJ; ++c) {
+                        const int slot = ((u - 2 * c) % R + R) % R;
+                        const bf16x8 tt = term == 1 ? tl[slot] : th[slot];
+                        const bf16x8 cc = term == 0 ? cll : chh;
+                        if constexpr (CONTIG)
+                            acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cc, tt, acc[c], 0, 0, 0);
+                        else
+                            acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tt, cc, acc[c], 0, 0, 0);
+                    }
+                // interleave the prefetch and conversion of the next steps with
+                // this step's MFMAs (one MFMA, then a few other instructions)
+#pragma unroll
+                for (int i = 0; i < 3 * NBJ; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+                    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+                    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // VALU
+                    __builtin_amdgcn_sched_group_barrier(0x004, 2, 0);  // SALU
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -614,9 +693,9 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
         float cb0[16], cbN[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t line = min(line0 + 8 * (r >> 2) + 4 * lh + (r & 3), lines - 1);
-            cb0[r] = Cb[line * n];
-            cbN[r] = Cb[line * n + N];
+            const int tl = 32 * wl + 8 * (r >> 2) + 4 * lh + (r & 3);
+            cb0[r] = w0s[tl];
+            cbN[r] = wNs[tl];
         }
 #pragma unroll
         for (int c = 0; c < NBJ; ++c) {
@@ -637,19 +716,24 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     } else {
         // rows = outputs j0 + 32 c + 8 (r / 4) + 4 lh + r % 4, columns = lines line0 + li
         const int64_t line = line0 + li;
-        const int64_t lc = min(line, lines - 1);
-        const float b0 = Cb[lc], bN = Cb[(int64_t)N * js + lc];
 #pragma unroll
         for (int c = 0; c < NBJ; ++c) {
             if (c < c_lo || c >= c_hi) continue;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int jl = 32 * c + 8 * (r >> 2) + 4 * lh + (r & 3), j = j0 + jl;
-                if (line < lines && j < n) {
-                    float v = acc[c][r];
-                    v = fmaf(c0s[jl], b0, v);
-                    v = fmaf(cNs[jl], bN, v);
-                    Pb[(int64_t)j * js + line] = v;
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int jl0 = 32 * c + 8 * r4 + 4 * lh;  // 4 consecutive outputs
+                const float4 k0 = *reinterpret_cast<const float4*>(c0s + jl0);
+                const float4 kN = *reinterpret_cast<const float4*>(cNs + jl0);
+                const float k0v[4] = {k0.x, k0.y, k0.z, k0.w}, kNv[4] = {kN.x, kN.y, kN.z, kN.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = j0 + jl0 + e;
+                    if (line < lines && j < n) {
+                        float v = acc[c][4 * r4 + e];
+                        v = fmaf(k0v[e], b0, v);
+                        v = fmaf(kNv[e], bN, v);
+                        Pb[(int64_t)j * js + line] = v;
+                    }
                 }
             }
         }
@@ -688,10 +772,10 @@ void ring_grid(FracLaunch& L, int64_t& grid, size_t& lds)
         L.first[a] = (int)grid;
         grid += (int64_t)L.tiles_m[a] * L.tiles_n[a] * (lay.contiguous ? 1 : lay.batches);
         const size_t kspan = (size_t)((op.n + 15) / 16) * 16;
-        size_t window = sizeof(uint32_t) * 2 * (32 * NBJ - 1 + kspan);
+        size_t window = sizeof(uint32_t) * 2 * (32 * NBJ + kspan);  // two planes of wpad words
         const size_t red = KSPLIT > 1 ? sizeof(float) * kWaves * NBJ * 16 * 64 : 0;
         window = window > red ? window : red;
-        const size_t need = sizeof(float) * 2 * 32 * NBJ + window;
+        const size_t need = sizeof(float) * (2 * 32 * NBJ + 2 * 32 * WL) + window;
         lds = need > lds ? need : lds;
     }
 }
@@ -738,6 +822,9 @@ hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s)
     case 7: return run_ring<8, 1, 4, 4>(L, s);
     case 8: return run_ring<8, 2, 2, 4>(L, s);
     case 9: return run_ring<8, 4, 1, 4>(L, s);
+    case 10: return run_ring<8, 1, 4, 8>(L, s);
+    case 11: return run_ring<8, 2, 2, 8>(L, s);
+    case 12: return run_ring<8, 4, 1, 8>(L, s);
     default: break;
     }
     // Register-ring kernel; the k loop is split across the wavefronts of a

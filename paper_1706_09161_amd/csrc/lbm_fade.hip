@@ -417,7 +417,7 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
         const size_t n = (size_t)grid->n[mu];
         W[mu] = make_axis_weights((int)n, 2.0 - params->alpha[mu], params->p[mu], params->g[mu], grid->dx);
         bytes += r256(sizeof(float) * (2 * n - 1)) + 2 * r256(sizeof(float) * n) +
-                 2 * r256(sizeof(uint16_t) * (2 * n - 1));
+                 2 * r256(sizeof(uint16_t) * (2 * n - 1)) + 2 * r256(sizeof(uint32_t) * lbm::pw_len_of((int)n));
     }
     auto cleanup = [&]() { lbm_fade_destroy(h); };
     hipError_t e = hipMalloc(&h->opmem, bytes);
@@ -443,6 +443,9 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
         const size_t oN = carve(sizeof(float) * n);
         const size_t oh = carve(sizeof(uint16_t) * (2 * n - 1));
         const size_t ol = carve(sizeof(uint16_t) * (2 * n - 1));
+        const int64_t pwn = lbm::pw_len_of(n);
+        const size_t oph = carve(sizeof(uint32_t) * pwn);
+        const size_t opl = carve(sizeof(uint32_t) * pwn);
         if (off > bytes) {
             cleanup();
             return fail(LBM_EINVAL, "internal: operator buffer overflow");
@@ -462,12 +465,27 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
             c0[j] = (float)W[mu].corr0[j];
             cN[j] = (float)W[mu].corrN[j];
         }
+        // pair words of the BF16 split, d decreasing (operand order of the BF16 GEMM)
+        uint32_t* pwh = reinterpret_cast<uint32_t*>(host.data() + oph);
+        uint32_t* pwl = reinterpret_cast<uint32_t*>(host.data() + opl);
+        const int top = lbm::pw_top_of(n);
+        auto bits = [&](const uint16_t* b, int64_t dd) -> uint32_t {
+            return (dd >= -(n - 1) && dd <= n - 1) ? (uint32_t)b[dd + n - 1] : 0u;
+        };
+        for (int64_t x = 0; x < pwn; ++x) {
+            const int64_t dd = top - x;
+            pwh[x] = bits(gh, dd) | (bits(gh, dd - 1) << 16);
+            pwl[x] = bits(glo, dd) | (bits(glo, dd - 1) << 16);
+        }
         unsigned char* base = reinterpret_cast<unsigned char*>(h->opmem);
         op.gen = reinterpret_cast<const float*>(base + og);
         op.corr0 = reinterpret_cast<const float*>(base + o0);
         op.corrN = reinterpret_cast<const float*>(base + oN);
         op.gen_hi = reinterpret_cast<const uint16_t*>(base + oh);
         op.gen_lo = reinterpret_cast<const uint16_t*>(base + ol);
+        op.pw_hi = reinterpret_cast<const uint32_t*>(base + oph);
+        op.pw_lo = reinterpret_cast<const uint32_t*>(base + opl);
+        op.pw_top = top;
     }
     if (off > bytes) {
         cleanup();
@@ -637,10 +655,16 @@ int lbm_fade_set_f(lbm_fade_t h, const float* src, int32_t on_device, void* stre
 
 int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t on_device, void* stream)
 {
-    if (!h || !C || !Phi) return fail(LBM_EINVAL, "null argument");
+    if (!h || !Phi) return fail(LBM_EINVAL, "null argument");
     int rc = check_device(h);
     if (rc) return rc;
     hipStream_t s = as_stream(stream);
+    if (!C) {
+        // the solver's own concentration (and, in split-BF16 mode, its packed split)
+        if (!h->has_state) return fail(LBM_ESTATE, "no state yet");
+        if (!on_device) return fail(LBM_EINVAL, "C = NULL needs a device Phi");
+        return run_phi(h, h->C, Phi, s);
+    }
     if (on_device) return run_phi(h, C, Phi, s);
     float *dC = nullptr, *dP = nullptr;
     if (hipMalloc(&dC, sizeof(float) * h->nodes) != hipSuccess ||

@@ -23,7 +23,17 @@ struct AxisOp {
     const float* corrN;  // n values
     const uint16_t* gen_hi;  // BF16 bits of T split hi/lo (same indexing)
     const uint16_t* gen_lo;
+    // Pair words of the split, W(d) = b(d) | b(d - 1) << 16 with b = hi or lo
+    // bits (0 for |d| > n - 1), stored with d decreasing: pw[x] = W(pw_top - x)
+    // for x in [0, pw_top + n + 32).  pw_top = 16 ceil((n + 512) / 16) - 1.
+    const uint32_t* pw_hi;
+    const uint32_t* pw_lo;
+    int pw_top;
 };
+
+// Top index and length of the pair-word arrays of an axis of n nodes.
+inline int pw_top_of(int n) { return 16 * ((n + 512 + 15) / 16) - 1; }
+inline int64_t pw_len_of(int n) { return (int64_t)pw_top_of(n) + n + 32; }
 
 // Strided view of a node field for the operator along one axis.
 //   contiguous axis (x): line l, node j  ->  l * n + j

@@ -174,6 +174,14 @@ class LbmFade:
         L.check(L.lib().lbm_fade_set_f(self._h, ptr, dev, _stream_ptr(stream)))
 
     def apply_phi(self, C, out=None, stream=None):
+        """Phi of every axis for the field C; C = None uses the solver's own
+        current concentration (device output; the GEMM launch of a step)."""
+        if C is None:
+            out, optr, odev = self._out(out, self.dim * self.nodes, (self.dim,) + self.shape, True)
+            if not odev:
+                raise ValueError("C = None needs a device output")
+            L.check(L.lib().lbm_fade_apply_phi(self._h, None, optr, 1, _stream_ptr(stream)))
+            return out
         dev_in = _is_cuda_tensor(C)
         ptr, dev, keep = self._in(C, self.nodes)
         out, optr, odev = self._out(out, self.dim * self.nodes, (self.dim,) + self.shape, bool(dev_in))

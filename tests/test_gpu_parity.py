@@ -97,7 +97,7 @@ TILE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("choice", [f"fp32:{c}" for c in range(1, 7)] + [f"bf16x3:{c}" for c in range(1, 10)])
+@pytest.mark.parametrize("choice", [f"fp32:{c}" for c in range(1, 7)] + [f"bf16x3:{c}" for c in range(1, 13)])
 @pytest.mark.parametrize("case", TILE_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
 def test_every_tile_configuration(case, choice, monkeypatch):
     """Each explicitly selectable GEMM configuration (LBM_FP32_TILE / LBM_BF16_TILE)
@@ -114,6 +114,24 @@ def test_every_tile_configuration(case, choice, monkeypatch):
         got = s.apply_phi(torch.from_numpy(C).cuda()).cpu().numpy().astype(np.float64)
     rel = 4 * max(n) * 2.0**-24 if precision == "fp32" else 2.0**-14
     assert np.all(np.abs(got - ref) <= rel * np.abs(ref) + 1e-30), np.max(np.abs(got - ref) / np.abs(ref))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_apply_phi_on_the_solver_state(precision):
+    """apply_phi(C = NULL) uses the solver's own C (and the split the collide
+    kernel wrote): bitwise equal to applying it to a copy of C."""
+    from paper_1706_09161_amd import LbmError, _lib
+
+    cfg = synth.small(2, [96, 80], alpha=[1.4, 1.7], p=[0.3, 0.6], seed=34)
+    with _solver(cfg, precision) as s:
+        with pytest.raises(LbmError) as ei:
+            s.apply_phi(None)
+        assert ei.value.code == _lib.LBM_ESTATE
+        s.set_C(synth.initial_C(cfg).astype(np.float32))
+        s.step(3)
+        a = s.apply_phi(None).cpu().numpy()
+        b = s.apply_phi(s.get_C()).cpu().numpy()
+    assert np.array_equal(a, b)
 
 
 def test_bf16x3_split_is_not_plain_bf16():
