@@ -427,6 +427,372 @@ hipError_t run_f32(FracLaunch& L, hipStream_t s)
     return go(fractional_f32_mfma<BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1, 1>);
 }
 
+// ---------------------------------------------------------------------------
+// Register-direct kernel.  One wavefront computes 32 lines x (32 NBJ) outputs
+// of one axis over its share of k with v_mfma_f32_32x32x2f32, in groups of 8 k
+// (4 MFMA steps of 2 k).  The k order inside a group is permuted so that each
+// lane consumes 4 consecutive k: at step s of group g the lane half lh works
+// on k = kw + 8 g + 4 lh + s (both operands use the same map, so the sum is
+// unchanged).  Hence
+//  * C comes straight from global memory into registers, P groups ahead, one
+//    16-byte load per lane and group along the contiguous axis (4 loads,
+//    coalesced across consecutive lines, along a strided axis); no LDS, no
+//    barrier in the k loop;
+//  * the Toeplitz values of a lane for one output block and group,
+//    T(d0), T(d0 - 1), T(d0 - 2), T(d0 - 3), are 4 consecutive words of an LDS
+//    window that stores T with d decreasing (two ds_read2 per block).
+// A workgroup has 4 wavefronts: WL line blocks x KSPLIT k-shares, summed
+// through LDS in a fixed order (deterministic).  Registers stay below 256 per
+// lane, so two workgroups share a CU and one's set-up and epilogue overlap the
+// other's MFMAs.
+template <bool CONTIG, int NBJ, int WL, int KSPLIT, int P, bool KFULL>
+__device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout& lay, const float* __restrict__ C,
+                                              float* __restrict__ Phi, int tiles_l, int tiles_j, int bid, int total,
+                                              unsigned char* smem)
+{
+    static_assert(WL * KSPLIT == kWaves, "4 wavefronts per workgroup");
+    constexpr int JT = 32 * NBJ;  // outputs per tile
+    static_assert(JT <= kThreads, "one thread per output of the tile");
+    constexpr int LT = 32 * WL;  // lines per tile
+    const int n = op.n, N = n - 1;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wl = wave / KSPLIT, wk = wave % KSPLIT;
+    const int li = lane & 31, lh = lane >> 5;
+
+    // tile of this workgroup: contiguous tile ranges per XCD; one-sided
+    // operators start their longest tiles first (see the split-BF16 kernel)
+    int lin = bid;
+    if ((total & 7) == 0) {
+        const int S = total >> 3, x = bid & 7, i = bid >> 3;
+        lin = x * S + i;
+        if ((op.lower_only || op.upper_only) && S % tiles_j == 0) {
+            const int lpx = S / tiles_j;
+            lin = x * S + (i % lpx) * tiles_j + i / lpx;
+        }
+    }
+    int jt = lin % tiles_j;
+    if (op.lower_only) jt = tiles_j - 1 - jt;
+    const int rest = lin / tiles_j;
+    const int lt = rest % tiles_l;
+    const int batch = rest / tiles_l;
+    const int j0 = jt * JT;
+    const int64_t lines = lay.lines;
+    const int64_t line0 = (int64_t)lt * LT + 32 * wl;
+    const int64_t js = lay.j_stride;
+    const float* Cb = C;
+    float* Pb = Phi;
+    if (!CONTIG) {
+        Cb += (int64_t)batch * lay.batch_stride;
+        Pb += (int64_t)batch * lay.batch_stride;
+    }
+
+    // k range in groups of 8 (one-sided operators skip the zero triangle)
+    int kb = 0, ke = n;
+    if (op.lower_only) ke = min(n, j0 + JT);
+    if (op.upper_only) kb = (min(j0, n - 1) / 8) * 8;
+    const int groups = (ke - kb + 7) / 8;  // >= 1
+    const int kend = kb + 8 * groups;
+    const int gpw = (groups + KSPLIT - 1) / KSPLIT;
+    const int g_first = wk * gpw;
+    const int my_groups = max(0, min(groups, g_first + gpw) - g_first);
+    const int kw = kb + 8 * min(g_first, groups - 1);
+    const int last = max(my_groups, 1) - 1;
+
+    // C of a group: lane = (line li, k half lh), 4 consecutive k
+    const int64_t my_line = min(line0 + li, lines - 1);  // rows past the end are computed, never stored
+    const float* q = CONTIG ? Cb + my_line * n + kw + 4 * lh : Cb + (int64_t)(kw + 4 * lh) * js + my_line;
+    auto load_c = [&](int g, f32x4& v) {
+        const int gc = min(g, last);
+        if constexpr (KFULL) {
+            if constexpr (CONTIG) {
+                v = *reinterpret_cast<const f32x4*>(q + 8 * gc);
+            } else {
+                const float* a = q + (int64_t)(8 * gc) * js;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = a[(int64_t)e * js];
+            }
+        } else {
+            const int k = kw + 8 * gc + 4 * lh;
+            const int64_t stride = CONTIG ? 1 : js;
+            const float* a = q + (int64_t)(8 * gc) * stride;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = k + e < n;
+                const float x = *(ok ? a + e * stride : Cb);
+                v[e] = ok ? x : 0.f;
+            }
+        }
+    };
+
+    // LDS: corr0 | corrN | C at the walls of each line (contiguous axis) |
+    // Toeplitz window, d decreasing (later the k-share reduction)
+    float* c0s = reinterpret_cast<float*>(smem);
+    float* cNs = c0s + JT;
+    float* w0s = cNs + JT;
+    float* wNs = w0s + LT;
+    float* win = wNs + LT;
+    const int wlen = JT - 1 + (kend - kb);  // word m holds T(dmax - m)
+    const int dmax = j0 + JT - 1 - kb;
+    constexpr int FU = 8;
+    auto fill_load = [&](int base, float (&v)[FU]) {
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int m = base + u * kThreads + threadIdx.x;
+            const int d = dmax - m;
+            v[u] = (m < wlen && d >= -N && d <= N) ? op.gen[d + N] : 0.f;
+        }
+    };
+    auto fill_store = [&](int base, const float (&v)[FU]) {
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int m = base + u * kThreads + threadIdx.x;
+            if (m < wlen) win[m] = v[u];
+        }
+    };
+    // loads complete in issue order: set-up loads first, then the C prefetch
+    float fv[FU];
+    fill_load(0, fv);
+    float cv0 = 0.f, cvN = 0.f, wv0 = 0.f, wvN = 0.f;
+    {
+        const int t = threadIdx.x;
+        if (t < JT && j0 + t < n) {
+            cv0 = op.corr0[j0 + t];
+            cvN = op.corrN[j0 + t];
+        }
+        if (CONTIG && t < LT) {
+            const int64_t line = min((int64_t)lt * LT + t, lines - 1);
+            wv0 = Cb[line * n];
+            wvN = Cb[line * n + N];
+        }
+    }
+    float b0 = 0.f, bN = 0.f;
+    if constexpr (!CONTIG) {
+        b0 = Cb[my_line];
+        bN = Cb[(int64_t)N * js + my_line];
+    }
+    f32x4 craw[P];
+#pragma unroll
+    for (int g = 0; g < P; ++g) load_c(g, craw[g]);
+    fill_store(0, fv);
+    {
+        const int t = threadIdx.x;
+        if (t < JT) {
+            c0s[t] = cv0;
+            cNs[t] = cvN;
+        }
+        if (CONTIG && t < LT) {
+            w0s[t] = wv0;
+            wNs[t] = wvN;
+        }
+    }
+    for (int base = FU * kThreads; base < wlen; base += FU * kThreads) {  // long axes only
+        fill_load(base, fv);
+        fill_store(base, fv);
+    }
+    __syncthreads();
+
+    f32x16 acc[NBJ];
+#pragma unroll
+    for (int c = 0; c < NBJ; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+
+    if (my_groups > 0) {
+        // Toeplitz values of block c, group g: window words m0 .. m0 + 3
+        const int mbase = dmax - j0 - li + kw + 4 * lh;
+        auto load_t = [&](int g, f32x4 (&tv)[NBJ]) {
+            const int gc = min(g, last);
+#pragma unroll
+            for (int c = 0; c < NBJ; ++c) {
+                const int m0 = mbase - 32 * c + 8 * gc;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) tv[c][e] = win[m0 + e];
+            }
+        };
+        f32x4 tf[2][NBJ];
+        load_t(0, tf[0]);
+        for (int g0 = 0; g0 < my_groups; g0 += 2 * P) {
+#pragma unroll
+            for (int u = 0; u < 2 * P; ++u) {
+                const int g = g0 + u;
+                // C of this group (zero past the end of the range), then reuse its slot for group g + P
+                f32x4 cur = craw[u % P];
+                if (g >= my_groups) cur = f32x4{0.f, 0.f, 0.f, 0.f};
+                load_c(g + P, craw[u % P]);
+                load_t(g + 1, tf[(u + 1) & 1]);
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+#pragma unroll
+                    for (int c = 0; c < NBJ; ++c) {
+                        if constexpr (CONTIG)
+                            acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[st], tf[u & 1][c][st], acc[c], 0, 0, 0);
+                        else
+                            acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(tf[u & 1][c][st], cur[st], acc[c], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int i = 0; i < 4 * NBJ; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+                    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+                    __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // VALU
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    int c_lo = 0, c_hi = NBJ;
+    if constexpr (KSPLIT > 1) {
+        __syncthreads();  // every wavefront is done with the window
+        float* red = win;
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                float4 v = make_float4(acc[c][4 * r4], acc[c][4 * r4 + 1], acc[c][4 * r4 + 2], acc[c][4 * r4 + 3]);
+                *reinterpret_cast<float4*>(red + (((wave * NBJ + c) * 4 + r4) * 64 + lane) * 4) = v;
+            }
+        __syncthreads();
+        c_lo = wk * (NBJ / KSPLIT);
+        c_hi = c_lo + NBJ / KSPLIT;
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c) {
+            if (c < c_lo || c >= c_hi) continue;
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int s = 0; s < KSPLIT; ++s) {
+                    const float4 v =
+                        *reinterpret_cast<const float4*>(red + ((((wl * KSPLIT + s) * NBJ + c) * 4 + r4) * 64 + lane) * 4);
+                    sum.x += v.x;
+                    sum.y += v.y;
+                    sum.z += v.z;
+                    sum.w += v.w;
+                }
+                acc[c][4 * r4] = sum.x;
+                acc[c][4 * r4 + 1] = sum.y;
+                acc[c][4 * r4 + 2] = sum.z;
+                acc[c][4 * r4 + 3] = sum.w;
+            }
+        }
+    }
+
+    // epilogue: boundary columns (rank-2 correction) and stores
+    if constexpr (CONTIG) {
+        float cb0[16], cbN[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int tl = 32 * wl + 8 * (r >> 2) + 4 * lh + (r & 3);
+            cb0[r] = w0s[tl];
+            cbN[r] = wNs[tl];
+        }
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c) {
+            if (c < c_lo || c >= c_hi) continue;
+            const int jl = 32 * c + li, j = j0 + jl;
+            const float k0 = c0s[jl], kN = cNs[jl];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t line = line0 + 8 * (r >> 2) + 4 * lh + (r & 3);
+                if (line < lines && j < n) {
+                    float v = acc[c][r];
+                    v = fmaf(k0, cb0[r], v);
+                    v = fmaf(kN, cbN[r], v);
+                    Pb[line * n + j] = v;
+                }
+            }
+        }
+    } else {
+        const int64_t line = line0 + li;
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c) {
+            if (c < c_lo || c >= c_hi) continue;
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int jl0 = 32 * c + 8 * r4 + 4 * lh;
+                const float4 k0 = *reinterpret_cast<const float4*>(c0s + jl0);
+                const float4 kN = *reinterpret_cast<const float4*>(cNs + jl0);
+                const float k0v[4] = {k0.x, k0.y, k0.z, k0.w}, kNv[4] = {kN.x, kN.y, kN.z, kN.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = j0 + jl0 + e;
+                    if (line < lines && j < n) {
+                        float v = acc[c][4 * r4 + e];
+                        v = fmaf(k0v[e], b0, v);
+                        v = fmaf(kNv[e], bN, v);
+                        Pb[(int64_t)j * js + line] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int NBJ, int WL, int KSPLIT, int P, bool KFULL>
+__global__ __launch_bounds__(kThreads, 2) void fractional_f32_ring(FracLaunch L)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_r[];
+    const int bid = blockIdx.x;
+    int axis = 0;
+    while (axis + 1 < L.naxes && bid >= L.first[axis + 1]) ++axis;
+    const int local = bid - L.first[axis];
+    const int total = L.first[axis + 1] - L.first[axis];
+    if (axis == 0)
+        f32_ring_tile<true, NBJ, WL, KSPLIT, P, KFULL>(L.op[0], L.lay[0], L.C[0], L.Phi[0], L.tiles_m[0], L.tiles_n[0],
+                                                       local, total, smem_r);
+    else
+        f32_ring_tile<false, NBJ, WL, KSPLIT, P, KFULL>(L.op[axis], L.lay[axis], L.C[axis], L.Phi[axis],
+                                                        L.tiles_m[axis], L.tiles_n[axis], local, total, smem_r);
+}
+
+// tiles_m = line tiles (32 WL lines), tiles_n = output tiles (32 NBJ outputs)
+template <int NBJ, int WL, int KSPLIT>
+void f32_ring_grid(FracLaunch& L, int64_t& grid, size_t& lds)
+{
+    grid = 0;
+    lds = 0;
+    for (int a = 0; a < L.naxes; ++a) {
+        const AxisOp& op = L.op[a];
+        const AxisLayout& lay = L.lay[a];
+        L.tiles_m[a] = (int)((lay.lines + 32 * WL - 1) / (32 * WL));
+        L.tiles_n[a] = (op.n + 32 * NBJ - 1) / (32 * NBJ);
+        L.first[a] = (int)grid;
+        grid += (int64_t)L.tiles_m[a] * L.tiles_n[a] * (lay.contiguous ? 1 : lay.batches);
+        const size_t kspan = (size_t)((op.n + 7) / 8) * 8;
+        size_t window = sizeof(float) * (32 * NBJ + kspan);
+        const size_t red = KSPLIT > 1 ? sizeof(float) * kWaves * NBJ * 16 * 64 : 0;
+        window = window > red ? window : red;
+        const size_t need = sizeof(float) * (2 * 32 * NBJ + 2 * 32 * WL) + window;
+        lds = need > lds ? need : lds;
+    }
+}
+
+template <int NBJ, int WL, int KSPLIT, int P>
+hipError_t run_f32_ring(FracLaunch& L, hipStream_t s)
+{
+    int64_t grid = 0;
+    size_t lds = 0;
+    f32_ring_grid<NBJ, WL, KSPLIT>(L, grid, lds);
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    L.first[L.naxes] = (int)grid;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    auto go = [&](auto kern) -> hipError_t {
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), lds, s, L);
+        return hipGetLastError();
+    };
+    bool kfull = true;  // every axis a multiple of 8: no group passes the end of an axis
+    for (int a = 0; a < L.naxes; ++a) kfull = kfull && (L.op[a].n % 8) == 0;
+    if (kfull) return go(fractional_f32_ring<NBJ, WL, KSPLIT, P, true>);
+    return go(fractional_f32_ring<NBJ, WL, KSPLIT, P, false>);
+}
+
 }  // namespace
 
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
@@ -469,10 +835,36 @@ hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxe
     case 4: return run_f32<64, 128, 64, 1, 2, 2>(L, s);
     case 5: return run_f32<128, 128, 32, 2, 2, 1>(L, s);
     case 6: return run_f32<128, 128, 64, 2, 2, 1>(L, s);
+    case 7: return run_f32_ring<4, 1, 4, 2>(L, s);
+    case 8: return run_f32_ring<4, 2, 2, 2>(L, s);
+    case 9: return run_f32_ring<4, 4, 1, 2>(L, s);
+    case 10: return run_f32_ring<8, 1, 4, 2>(L, s);
+    case 11: return run_f32_ring<8, 2, 2, 2>(L, s);
+    case 12: return run_f32_ring<8, 4, 1, 2>(L, s);
     default: break;
     }
-    if (big_tiles(L) < 512) return run_f32<64, 64, 128, 1, 1, 4>(L, s);
-    return run_f32<128, 128, 32, 2, 2, 1>(L, s);
+    // Register-direct kernel.  Output tiles of 256 when every axis fits in
+    // one (C is then read once per axis), else of 128; the k loop is split
+    // over the wavefronts of a workgroup (1, 2 or 4 ways: the smallest split
+    // that gives >= 512 workgroups and <= 128 groups of 8 k per wavefront).
+    int nmax = 0;
+    for (int a = 0; a < L.naxes; ++a) nmax = L.op[a].n > nmax ? L.op[a].n : nmax;
+    const int kgroups = (nmax + 7) / 8;
+    FracLaunch T = L;
+    int64_t grid = 0;
+    size_t lds = 0;
+    if (nmax <= 256) {
+        f32_ring_grid<8, 4, 1>(T, grid, lds);
+        if (grid >= 512) return run_f32_ring<8, 4, 1, 2>(L, s);
+        f32_ring_grid<8, 2, 2>(T, grid, lds);
+        if (grid >= 512) return run_f32_ring<8, 2, 2, 2>(L, s);
+        return run_f32_ring<8, 1, 4, 2>(L, s);
+    }
+    f32_ring_grid<4, 4, 1>(T, grid, lds);
+    if (grid >= 512 && kgroups <= 128) return run_f32_ring<4, 4, 1, 2>(L, s);
+    f32_ring_grid<4, 2, 2>(T, grid, lds);
+    if (grid >= 512 && (kgroups + 1) / 2 <= 128) return run_f32_ring<4, 2, 2, 2>(L, s);
+    return run_f32_ring<4, 1, 4, 2>(L, s);
 }
 
 int64_t big_tiles(const FracLaunch& L)
