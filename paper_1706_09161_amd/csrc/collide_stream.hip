@@ -85,9 +85,8 @@ __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q]
 }
 
 // ---------------------------------------------------------------------------
-// 2D D2Q5 fused kernel.  The inputs of row y + 2 are requested before row y + 1
-// is collided and row y is written, so two rows of loads are in flight per
-// wavefront.
+// 2D D2Q5 fused kernel.  Rows move through a ring of D slots: while row y + 1
+// is collided, the loads of rows y + 2 .. y + D are in flight.
 template <bool HAS_S, bool PACK>
 __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
                                                          float* __restrict__ fout, const float* __restrict__ Phi,
@@ -95,6 +94,7 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
                                                          uint32_t* __restrict__ Cpout, int rows_per_wave,
                                                          int strips, int total_waves)
 {
+    constexpr int D = 4;
     const int nx = cc.n[0], ny = cc.n[1];
     const int64_t nodes = (int64_t)nx * ny;
     const int lane = threadIdx.x & 63;
@@ -110,84 +110,83 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
     struct Row {
         float f[5], phi[2], s;
     };
+    // Rows and columns outside the box read the nearest node inside it: every
+    // population they send into the box arrives through a wall and is replaced
+    // by the Dirichlet rule, and they are never stored, so their values do not
+    // matter (and the loads need no guard, no branch, no early wait).
+    const int64_t xc = min(max(x, 0), nx - 1);
     auto load_row = [&](int y, Row& r) {
-        if (col_ok && y >= 0 && y < ny) {
-            const int64_t node = (int64_t)y * nx + x;
+        const int64_t node = (int64_t)min(max(y, 0), ny - 1) * nx + xc;
 #pragma unroll
-            for (int i = 0; i < 5; ++i) r.f[i] = fin[i * nodes + node];
-            r.phi[0] = Phi[node];
-            r.phi[1] = Phi[nodes + node];
-            r.s = HAS_S ? S[node] : 0.f;
-        } else {
-#pragma unroll
-            for (int i = 0; i < 5; ++i) r.f[i] = 0.f;
-            r.phi[0] = r.phi[1] = 0.f;
-            r.s = 0.f;
-        }
+        for (int i = 0; i < 5; ++i) r.f[i] = fin[i * nodes + node];
+        r.phi[0] = Phi[node];
+        r.phi[1] = Phi[nodes + node];
+        r.s = HAS_S ? S[node] : 0.f;
     };
     auto collide_row = [&](const Row& r, float (&fs)[5]) { collide_node<5>(cc, r.f, r.phi, r.s, fs); };
 
-    float prev3 = 0.f;
-    float cur[5], nxt[5];
-    Row ra, rb;
-    if (y0 >= 1) {
-        load_row(y0 - 1, ra);
+    Row ring[D];
+    load_row(y0 - 1, ring[D - 1]);  // halo row below the chunk (its f*_3 enters row y0)
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k) load_row(y0 + k, ring[k]);
+    float prev3, cur[5];
+    {
         float t[5];
-        collide_row(ra, t);
+        collide_row(ring[D - 1], t);
         prev3 = t[3];
     }
-    load_row(y0, ra);
-    load_row(y0 + 1, rb);  // row y0 + 1 (zeros past the top wall)
-    collide_row(ra, cur);
-    for (int y = y0; y < y1; ++y) {
-        const bool has_next = (y + 1 < ny);
-        Row rc;
-        load_row(y + 2, rc);  // prefetch
-        if (has_next) {
-            collide_row(rb, nxt);
-        } else {
+    load_row(y0 + D - 1, ring[D - 1]);
+    collide_row(ring[0], cur);
+    for (int yb = y0; yb < y1; yb += D) {
 #pragma unroll
-            for (int i = 0; i < 5; ++i) nxt[i] = 0.f;
-        }
-        // pull: f_1 from x-1, f_2 from x+1 (lane shuffles), f_3 from y-1, f_4 from y+1
-        const float from_left = __shfl_up(cur[1], 1, 64);
-        const float from_right = __shfl_down(cur[2], 1, 64);
-        float f[5] = {cur[0], from_left, from_right, prev3, nxt[4]};
-        bool unk[5] = {false, x == 0, x == nx - 1, y == 0, y == ny - 1};
-        int nu = 0;
-        float known = 0.f;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            if (unk[i]) ++nu;
-            else known += f[i];
-        }
-        if (nu > 0) {
-            const float share = (cc.c_wall - known) / (float)nu;
-#pragma unroll
-            for (int i = 0; i < 5; ++i)
-                if (unk[i]) f[i] = share;
-        }
-        if (out_lane) {
-            const int64_t node = (int64_t)y * nx + x;
-            float c = 0.f;
+        for (int u = 0; u < D; ++u) {
+            const int y = yb + u;
+            // slot u held row y (collided into cur): refill it with row y + D
+            load_row(y + D, ring[u]);
+            float nxt[5];
+            collide_row(ring[(u + 1) % D], nxt);  // row y + 1
+            // pull: f_1 from x-1, f_2 from x+1 (lane shuffles), f_3 from y-1, f_4 from y+1
+            const float from_left = __shfl_up(cur[1], 1, 64);
+            const float from_right = __shfl_down(cur[2], 1, 64);
+            float f[5] = {cur[0], from_left, from_right, prev3, nxt[4]};
+            const bool unk[5] = {false, x == 0, x == nx - 1, y == 0, y == ny - 1};
+            int nu = 0;
+            float known = 0.f;
 #pragma unroll
             for (int i = 0; i < 5; ++i) {
-                fout[i * nodes + node] = f[i];
-                c += f[i];
+                if (unk[i]) ++nu;
+                else known += f[i];
             }
-            Cout[node] = c;
-            if (PACK) Cpout[node] = pack_hilo(c);
-        }
-        prev3 = cur[3];
+            if (nu > 0) {
+                const float share = (cc.c_wall - known) / (float)nu;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) cur[i] = nxt[i];
-        rb = rc;
+                for (int i = 0; i < 5; ++i)
+                    if (unk[i]) f[i] = share;
+            }
+            if (out_lane && y < y1) {
+                const int64_t node = (int64_t)y * nx + x;
+                float c = 0.f;
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    fout[i * nodes + node] = f[i];
+                    c += f[i];
+                }
+                Cout[node] = c;
+                if (PACK) Cpout[node] = pack_hilo(c);
+            }
+            prev3 = cur[3];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) cur[i] = nxt[i];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // 3D D3Q7 fused kernel: workgroup = NY wavefronts (one per y row), rows 0 and
-// NY-1 of the workgroup are halo rows; marches along z.
+// NY-1 of the workgroup are halo rows; marches along z with a ring of D
+// planes (the loads of planes z + 2 .. z + D are in flight while plane z + 1
+// is collided).  f*_3 / f*_4 cross rows through LDS, double-buffered by plane
+// parity so one barrier per plane suffices.
 template <int NY, bool HAS_S, bool PACK>
 __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, const float* __restrict__ fin,
                                                              float* __restrict__ fout, const float* __restrict__ Phi,
@@ -195,6 +194,7 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
                                                              uint32_t* __restrict__ Cpout, int planes_per_block,
                                                              int strips_x, int strips_y)
 {
+    constexpr int D = 3;
     const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
     const int64_t plane = (int64_t)nx * ny;
     const int64_t nodes = plane * nz;
@@ -211,90 +211,82 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
     const int z0 = chunk * planes_per_block;
     const int z1 = min(nz, z0 + planes_per_block);
 
-    // f*_3 (moving +y) and f*_4 (moving -y) of the current plane, exchanged between rows
-    __shared__ float sh3[NY][64];
-    __shared__ float sh4[NY][64];
+    // f*_3 (moving +y) and f*_4 (moving -y) of the current plane, by plane parity
+    __shared__ float sh3[2][NY][64];
+    __shared__ float sh4[2][NY][64];
 
     struct Plane {
         float f[7], phi[3], s;
     };
+    // nodes outside the box read the nearest node inside it (see the 2D kernel)
+    const int64_t xyc = (int64_t)min(max(y, 0), ny - 1) * nx + min(max(x, 0), nx - 1);
     auto load_at = [&](int z, Plane& p) {
-        if (ok && z >= 0 && z < nz) {
-            const int64_t node = (int64_t)z * plane + (int64_t)y * nx + x;
+        const int64_t node = (int64_t)min(max(z, 0), nz - 1) * plane + xyc;
 #pragma unroll
-            for (int i = 0; i < 7; ++i) p.f[i] = fin[i * nodes + node];
+        for (int i = 0; i < 7; ++i) p.f[i] = fin[i * nodes + node];
 #pragma unroll
-            for (int mu = 0; mu < 3; ++mu) p.phi[mu] = Phi[mu * nodes + node];
-            p.s = HAS_S ? S[node] : 0.f;
-        } else {
-#pragma unroll
-            for (int i = 0; i < 7; ++i) p.f[i] = 0.f;
-            p.phi[0] = p.phi[1] = p.phi[2] = 0.f;
-            p.s = 0.f;
-        }
+        for (int mu = 0; mu < 3; ++mu) p.phi[mu] = Phi[mu * nodes + node];
+        p.s = HAS_S ? S[node] : 0.f;
     };
     auto collide_at = [&](const Plane& p, float (&fs)[7]) { collide_node<7>(cc, p.f, p.phi, p.s, fs); };
 
-    float prev5 = 0.f;
-    float cur[7], nxt[7];
-    Plane pa, pb;
-    if (z0 >= 1) {
-        load_at(z0 - 1, pa);
+    Plane ring[D];
+    load_at(z0 - 1, ring[D - 1]);  // halo plane below the chunk
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k) load_at(z0 + k, ring[k]);
+    float prev5, cur[7];
+    {
         float t[7];
-        collide_at(pa, t);
+        collide_at(ring[D - 1], t);
         prev5 = t[5];
     }
-    load_at(z0, pa);
-    load_at(z0 + 1, pb);
-    collide_at(pa, cur);
-    for (int z = z0; z < z1; ++z) {
-        const bool has_next = (z + 1 < nz);
-        Plane pc;
-        load_at(z + 2, pc);  // prefetch
-        if (has_next) {
-            collide_at(pb, nxt);
-        } else {
+    load_at(z0 + D - 1, ring[D - 1]);
+    collide_at(ring[0], cur);
+    for (int zb = z0; zb < z1; zb += D) {
 #pragma unroll
-            for (int i = 0; i < 7; ++i) nxt[i] = 0.f;
-        }
-        sh3[row][lane] = cur[3];
-        sh4[row][lane] = cur[4];
-        __syncthreads();
-        const float from_left = __shfl_up(cur[1], 1, 64);
-        const float from_right = __shfl_down(cur[2], 1, 64);
-        const float from_below = row >= 1 ? sh3[row - 1][lane] : 0.f;   // f*_3 of y-1
-        const float from_above = row + 1 < NY ? sh4[row + 1][lane] : 0.f;  // f*_4 of y+1
-        float f[7] = {cur[0], from_left, from_right, from_below, from_above, prev5, nxt[6]};
-        bool unk[7] = {false, x == 0, x == nx - 1, y == 0, y == ny - 1, z == 0, z == nz - 1};
-        int nu = 0;
-        float known = 0.f;
-#pragma unroll
-        for (int i = 0; i < 7; ++i) {
-            if (unk[i]) ++nu;
-            else known += f[i];
-        }
-        if (nu > 0) {
-            const float share = (cc.c_wall - known) / (float)nu;
-#pragma unroll
-            for (int i = 0; i < 7; ++i)
-                if (unk[i]) f[i] = share;
-        }
-        if (out) {
-            const int64_t node = (int64_t)z * plane + (int64_t)y * nx + x;
-            float c = 0.f;
+        for (int u = 0; u < D; ++u) {
+            const int z = zb + u;
+            const int par = (z - z0) & 1;
+            sh3[par][row][lane] = cur[3];
+            sh4[par][row][lane] = cur[4];
+            load_at(z + D, ring[u]);
+            float nxt[7];
+            collide_at(ring[(u + 1) % D], nxt);  // plane z + 1
+            lds_barrier();
+            const float from_left = __shfl_up(cur[1], 1, 64);
+            const float from_right = __shfl_down(cur[2], 1, 64);
+            const float from_below = row >= 1 ? sh3[par][row - 1][lane] : 0.f;       // f*_3 of y-1
+            const float from_above = row + 1 < NY ? sh4[par][row + 1][lane] : 0.f;  // f*_4 of y+1
+            float f[7] = {cur[0], from_left, from_right, from_below, from_above, prev5, nxt[6]};
+            const bool unk[7] = {false, x == 0, x == nx - 1, y == 0, y == ny - 1, z == 0, z == nz - 1};
+            int nu = 0;
+            float known = 0.f;
 #pragma unroll
             for (int i = 0; i < 7; ++i) {
-                fout[i * nodes + node] = f[i];
-                c += f[i];
+                if (unk[i]) ++nu;
+                else known += f[i];
             }
-            Cout[node] = c;
-            if (PACK) Cpout[node] = pack_hilo(c);
-        }
-        __syncthreads();  // sh3/sh4 are rewritten in the next plane
-        prev5 = cur[5];
+            if (nu > 0) {
+                const float share = (cc.c_wall - known) / (float)nu;
 #pragma unroll
-        for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
-        pb = pc;
+                for (int i = 0; i < 7; ++i)
+                    if (unk[i]) f[i] = share;
+            }
+            if (out && z < z1) {
+                const int64_t node = (int64_t)z * plane + (int64_t)y * nx + x;
+                float c = 0.f;
+#pragma unroll
+                for (int i = 0; i < 7; ++i) {
+                    fout[i * nodes + node] = f[i];
+                    c += f[i];
+                }
+                Cout[node] = c;
+                if (PACK) Cpout[node] = pack_hilo(c);
+            }
+            prev5 = cur[5];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
+        }
     }
 }
 
@@ -411,12 +403,13 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         }
         return hipGetLastError();
     }
-    constexpr int NY = 8;
+    constexpr int NY = 16;
     const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
     const int sx = (nx + kStrip - 1) / kStrip;
     const int sy = (ny + (NY - 2) - 1) / (NY - 2);
+    // long z marches amortise the two halo planes; at least 2 workgroups per CU
     int planes = 64;
-    while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 2048) planes /= 2;
+    while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 512) planes /= 2;
     const int chunks = (nz + planes - 1) / planes;
     const int64_t blocks = (int64_t)sx * sy * chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;

@@ -590,7 +590,7 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
         fill_load(base, fv);
         fill_store(base, fv);
     }
-    __syncthreads();
+    lds_barrier();  // the C prefetch stays in flight
 
     f32x16 acc[NBJ];
 #pragma unroll

@@ -584,7 +584,7 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
         fill_load(base, fv);
         fill_store(base, fv);
     }
-    __syncthreads();
+    lds_barrier();  // the C prefetch stays in flight
 
     f32x16 acc[NBJ];
 #pragma unroll

@@ -35,6 +35,16 @@ struct AxisOp {
 inline int pw_top_of(int n) { return 16 * ((n + 512 + 15) / 16) - 1; }
 inline int64_t pw_len_of(int n) { return (int64_t)pw_top_of(n) + n + 32; }
 
+// Workgroup barrier that orders LDS accesses only (release/acquire fences
+// scoped to LDS): global loads in flight stay in flight, unlike
+// __syncthreads(), which also waits for them.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Strided view of a node field for the operator along one axis.
 //   contiguous axis (x): line l, node j  ->  l * n + j
 //   other axes: batch b, node j, line l  ->  b * batch_stride + j * j_stride + l
