@@ -50,6 +50,13 @@ def gemm_flops_per_step(cfg: dict) -> float:
     return total
 
 
+def gemm_bytes_per_step(cfg: dict) -> float:
+    """Algorithmic HBM bytes of the FP32 GEMM launch: C read once per axis, the
+    d fractional terms written (FP32)."""
+    d = cfg["dim"]
+    return 2.0 * d * 4.0 * float(np.prod(cfg["n"][:d]))
+
+
 def collide_bytes_per_step(cfg: dict) -> float:
     """Algorithmic HBM bytes of the fused collide-stream kernel: Q populations
     read and written, d fractional terms read, C written (FP32)."""
@@ -97,6 +104,64 @@ def time_gemm(torch, solver, reps: int) -> float:
     end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end) / 1e3 / reps
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_fp32__2d_1024sq_pmc.txt")
+GEMM_SOURCES = [os.path.join(ROOT, "paper_1706_09161_amd", "csrc", f) for f in ("fractional_gemm.hip", "lbm_internal.h")]
+
+
+def gemm_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 GEMM from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a plain copy of known size); None when the summary is missing
+    or was taken from other GEMM sources than the ones built now."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != gemm_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def profile_run(torch, LbmFade, synth, reps: int = 20):
+    """Launch sequence for rocprofv3 (trace or counters): a plain 256 MiB copy
+    (the calibration of FETCH_SIZE / WRITE_SIZE), then, per precision, `reps`
+    launches of the fractional-term GEMM on the solver's own C and `reps`
+    steps of the benchmark workload."""
+    a = torch.ones(64 * 1024 * 1024, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    cfg = synth.config(WORKLOAD)
+    C0 = torch.from_numpy(synth.initial_C(cfg).astype(np.float32)).cuda()
+    for precision in ("fp32", "bf16x3"):
+        with LbmFade.from_config(cfg, precision=precision) as s:
+            s.set_C(C0)
+            out = torch.empty((cfg["dim"],) + tuple(C0.shape), device="cuda")
+            for _ in range(reps):
+                s.apply_phi(None, out=out)
+            s.step(reps)
+            torch.cuda.synchronize()
+    log("profile run done")
 
 
 def adjoint_ratio(torch, LbmFade, synth):
@@ -152,6 +217,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the full-length accuracy runs")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the launch sequence profiled by rocprofv3 (copy calibration, GEMM, steps); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -166,6 +233,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.profile_run:
+        profile_run(torch, LbmFade, synth)
+        return
     cfg = synth.config(WORKLOAD)
     d = cfg["dim"]
     nodes = int(np.prod(cfg["n"][:d]))
@@ -216,9 +286,11 @@ def main():
                    "nodes": nodes, "workload_steps": cfg["steps"]},
         "rel_l2_vs_fp64_oracle": r["err"],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp32_mfma_TFLOPs"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32_mfma_TFLOPs"], 4), "traffic": None,
-                     "kernel": "fractional-term GEMM (x-axis and y-axis launches of one step)",
-                     "flops_per_step": flops, "avg_us_per_step": r["gemm_s"] * 1e6},
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32_mfma_TFLOPs"], 4),
+                     "traffic": measured_traffic(),
+                     "kernel": "fractional-term GEMM, FP32 (one launch: x and y axes of a step)",
+                     "flops_per_launch": flops, "avg_us_per_launch": r["gemm_s"] * 1e6,
+                     "algorithmic_bytes_per_launch": gemm_bytes_per_step(cfg)},
         "collide_stream": {"bound": "hbm", "est_us_per_step": collide_s * 1e6,
                            "algorithmic_bytes_per_step": collide_bytes_per_step(cfg),
                            "achieved_GBps": collide_bytes_per_step(cfg) / collide_s / 1e9,
