@@ -16,17 +16,23 @@
 //      corners);
 //   5. and writes the new f and C = sum_i f_i.
 //
-// 2D (D2Q5): each wavefront owns a strip of 64 columns (62 outputs plus one
-// halo column per side, whose f*_1 / f*_2 reach the neighbours through lane
-// shuffles) and marches up the y axis: the collision of row y+1 is computed
-// once, its f*_4 is used for row y and its f*_3 for row y+2.  Every node is
-// collided once (plus 2 halo columns per 62 and 2 halo rows per chunk), every
-// population is read once and written once: (2Q + d + 1) * 4 bytes per node
-// from HBM (52 B for D2Q5).
+// 2D (D2Q5): each wavefront owns a strip of 64 columns starting on a
+// multiple of 64 (its loads and stores are whole 128-byte lines) and marches
+// up the y axis: the collision of row y+1 is computed once, its f*_4 is used
+// for row y and its f*_3 for row y+2.  f*_1 / f*_2 cross columns by lane
+// shuffles; at the strip's two edges lanes 0 and 63 also read the node just
+// outside the strip and compute the one population that crosses (one row of
+// the collision operator).  Every node is collided once (plus 2 halo rows per
+// march), every population is read once and written once: (2Q + d + 1) * 4
+// bytes per node from HBM (52 B for D2Q5).
 //
-// 3D (D3Q7): a workgroup of NY wavefronts covers 64 x NY nodes of one z plane
-// (one wave per y row, rows 0 and NY-1 halo) and marches along z; f*_3/f*_4
-// cross rows through LDS, f*_5/f*_6 cross planes in registers.
+// 3D (D3Q7): a workgroup of NY wavefronts covers 64 x (NY - 2) nodes of one z
+// plane (one wave per y row, rows 0 and NY-1 halo, the x edges as in 2D) and
+// marches along z; f*_3/f*_4 cross rows through LDS, f*_5/f*_6 cross planes in
+// registers.
+//
+// Offsets are 32-bit byte offsets from uniform base pointers (one VALU add per
+// address) while every array fits in 4 GiB, 64-bit otherwise.
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 
@@ -35,7 +41,21 @@
 namespace lbm {
 namespace {
 
-constexpr int kStrip = 62;  // output columns per wavefront (64 lanes minus 2 halo)
+constexpr int kStrip = 64;  // output columns per wavefront
+
+// 1 / (number of unknown populations) of the Dirichlet rule (at most 3)
+__device__ __forceinline__ float inv_count(int nu) { return nu == 1 ? 1.f : (nu == 2 ? 0.5f : 1.f / 3.f); }
+
+template <typename OFF>
+__device__ __forceinline__ float ldf(const float* base, OFF boff)
+{
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename OFF, typename T>
+__device__ __forceinline__ void stv(T* base, OFF boff, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+}
 
 // BF16 split of C for the split-BF16 fractional term: hi = bf16(c),
 // lo = bf16(c - hi), both round to nearest even, packed hi | lo << 16.
@@ -84,10 +104,42 @@ __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q]
     }
 }
 
+// Post-collision populations a and b of one node (a halo node at a strip edge).
+template <int Q>
+__device__ inline void collide_two(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
+                                   float S, int a, int b, float& fa, float& fb)
+{
+    constexpr int d = (Q - 1) / 2;
+    float C = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) C += f[i];
+    float feq[Q];
+    float sphi = 0.f;
+#pragma unroll
+    for (int mu = 0; mu < d; ++mu) sphi += phi[mu];
+    feq[0] = C - cc.w[0] * sphi;
+#pragma unroll
+    for (int mu = 0; mu < d; ++mu) {
+        const float x = cc.w[2 * mu + 1] * phi[mu];
+        const float y = cc.adv[mu] * C;
+        feq[2 * mu + 1] = x + y;
+        feq[2 * mu + 2] = x - y;
+    }
+    float ra = 0.f, rb = 0.f;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const float dev = f[j] - feq[j];
+        ra = fmaf(cc.R[a * Q + j], dev, ra);
+        rb = fmaf(cc.R[b * Q + j], dev, rb);
+    }
+    fa = fmaf(cc.wSdt[a], S, f[a] - ra);
+    fb = fmaf(cc.wSdt[b], S, f[b] - rb);
+}
+
 // ---------------------------------------------------------------------------
 // 2D D2Q5 fused kernel.  Rows move through a ring of D slots: while row y + 1
 // is collided, the loads of rows y + 2 .. y + D are in flight.
-template <bool HAS_S, bool PACK>
+template <bool HAS_S, bool PACK, typename OFF>
 __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
                                                          float* __restrict__ fout, const float* __restrict__ Phi,
                                                          const float* __restrict__ S, float* __restrict__ Cout,
@@ -101,53 +153,76 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
     const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (gw >= total_waves) return;  // whole wavefront exits together
     const int strip = gw % strips, chunk = gw / strips;
-    const int x = strip * kStrip - 1 + lane;
-    const bool col_ok = (x >= 0) && (x < nx);
-    const bool out_lane = col_ok && lane >= 1 && lane <= kStrip;
+    const int x0 = strip * kStrip;
+    const int x = x0 + lane;
+    const bool out_lane = x < nx;
     const int y0 = chunk * rows_per_wave;
     const int y1 = min(ny, y0 + rows_per_wave);
 
-    struct Row {
-        float f[5], phi[2], s;
-    };
-    // Rows and columns outside the box read the nearest node inside it: every
-    // population they send into the box arrives through a wall and is replaced
-    // by the Dirichlet rule, and they are never stored, so their values do not
-    // matter (and the loads need no guard, no branch, no early wait).
-    const int64_t xc = min(max(x, 0), nx - 1);
-    auto load_row = [&](int y, Row& r) {
-        const int64_t node = (int64_t)min(max(y, 0), ny - 1) * nx + xc;
+    // uniform base pointers of every array
+    const float* fi[5];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) r.f[i] = fin[i * nodes + node];
-        r.phi[0] = Phi[node];
-        r.phi[1] = Phi[nodes + node];
-        r.s = HAS_S ? S[node] : 0.f;
+    for (int i = 0; i < 5; ++i) fi[i] = fin + i * nodes;
+    const float* ph1 = Phi + nodes;
+
+    struct Row {
+        float f[5], phi[2], s;  // this lane's node
+        float h[5], hphi[2], hs;  // the node just outside the strip (left half: x0 - 1, right half: x0 + 64)
     };
-    auto collide_row = [&](const Row& r, float (&fs)[5]) { collide_node<5>(cc, r.f, r.phi, r.s, fs); };
+    // Nodes outside the box read the nearest node inside it: every population
+    // they send into the box arrives through a wall and is replaced by the
+    // Dirichlet rule, and they are never stored, so their values do not matter
+    // (and the loads need no guard, no branch, no early wait).
+    const int xc = min(x, nx - 1);
+    const int hx = lane < 32 ? max(x0 - 1, 0) : min(x0 + kStrip, nx - 1);
+    auto load_row = [&](int y, Row& r) {
+        const int64_t rowoff = (int64_t)min(max(y, 0), ny - 1) * nx;
+        const OFF b = (OFF)((rowoff + xc) * 4), bh = (OFF)((rowoff + hx) * 4);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) r.f[i] = ldf(fi[i], b);
+        r.phi[0] = ldf(Phi, b);
+        r.phi[1] = ldf(ph1, b);
+        r.s = HAS_S ? ldf(S, b) : 0.f;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) r.h[i] = ldf(fi[i], bh);
+        r.hphi[0] = ldf(Phi, bh);
+        r.hphi[1] = ldf(ph1, bh);
+        r.hs = HAS_S ? ldf(S, bh) : 0.f;
+    };
+    // collision of a row: this lane's node, and the population its halo node
+    // sends into the strip (f*_1 from the left neighbour, f*_2 from the right)
+    auto collide_row = [&](const Row& r, float (&fs)[5], float& hv) {
+        collide_node<5>(cc, r.f, r.phi, r.s, fs);
+        float h1, h2;
+        collide_two<5>(cc, r.h, r.hphi, r.hs, 1, 2, h1, h2);
+        hv = lane < 32 ? h1 : h2;
+    };
 
     Row ring[D];
     load_row(y0 - 1, ring[D - 1]);  // halo row below the chunk (its f*_3 enters row y0)
 #pragma unroll
     for (int k = 0; k < D - 1; ++k) load_row(y0 + k, ring[k]);
-    float prev3, cur[5];
+    float prev3, cur[5], hcur;
     {
-        float t[5];
-        collide_row(ring[D - 1], t);
+        float t[5], th;
+        collide_row(ring[D - 1], t, th);
         prev3 = t[3];
     }
     load_row(y0 + D - 1, ring[D - 1]);
-    collide_row(ring[0], cur);
+    collide_row(ring[0], cur, hcur);
     for (int yb = y0; yb < y1; yb += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
             const int y = yb + u;
             // slot u held row y (collided into cur): refill it with row y + D
             load_row(y + D, ring[u]);
-            float nxt[5];
-            collide_row(ring[(u + 1) % D], nxt);  // row y + 1
-            // pull: f_1 from x-1, f_2 from x+1 (lane shuffles), f_3 from y-1, f_4 from y+1
-            const float from_left = __shfl_up(cur[1], 1, 64);
-            const float from_right = __shfl_down(cur[2], 1, 64);
+            float nxt[5], hnxt;
+            collide_row(ring[(u + 1) % D], nxt, hnxt);  // row y + 1
+            // pull: f_1 from x-1, f_2 from x+1, f_3 from y-1, f_4 from y+1
+            const float sl = __shfl_up(cur[1], 1, 64);
+            const float sr = __shfl_down(cur[2], 1, 64);
+            const float from_left = lane == 0 ? hcur : sl;
+            const float from_right = lane == 63 ? hcur : sr;
             float f[5] = {cur[0], from_left, from_right, prev3, nxt[4]};
             const bool unk[5] = {false, x == 0, x == nx - 1, y == 0, y == ny - 1};
             int nu = 0;
@@ -158,25 +233,26 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
                 else known += f[i];
             }
             if (nu > 0) {
-                const float share = (cc.c_wall - known) / (float)nu;
+                const float share = (cc.c_wall - known) * inv_count(nu);
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
                     if (unk[i]) f[i] = share;
             }
             if (out_lane && y < y1) {
-                const int64_t node = (int64_t)y * nx + x;
+                const OFF b = (OFF)(((int64_t)y * nx + x) * 4);
                 float c = 0.f;
 #pragma unroll
                 for (int i = 0; i < 5; ++i) {
-                    fout[i * nodes + node] = f[i];
+                    stv(fout + i * nodes, b, f[i]);
                     c += f[i];
                 }
-                Cout[node] = c;
-                if (PACK) Cpout[node] = pack_hilo(c);
+                stv(Cout, b, c);
+                if (PACK) stv(Cpout, b, pack_hilo(c));
             }
             prev3 = cur[3];
 #pragma unroll
             for (int i = 0; i < 5; ++i) cur[i] = nxt[i];
+            hcur = hnxt;
         }
     }
 }
@@ -187,7 +263,7 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
 // planes (the loads of planes z + 2 .. z + D are in flight while plane z + 1
 // is collided).  f*_3 / f*_4 cross rows through LDS, double-buffered by plane
 // parity so one barrier per plane suffices.
-template <int NY, bool HAS_S, bool PACK>
+template <int NY, bool HAS_S, bool PACK, typename OFF>
 __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, const float* __restrict__ fin,
                                                              float* __restrict__ fout, const float* __restrict__ Phi,
                                                              const float* __restrict__ S, float* __restrict__ Cout,
@@ -204,10 +280,10 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
     b /= strips_x;
     const int sy = b % strips_y;
     const int chunk = b / strips_y;
-    const int x = sx * kStrip - 1 + lane;
+    const int x0 = sx * kStrip;
+    const int x = x0 + lane;
     const int y = sy * (NY - 2) - 1 + row;
-    const bool ok = (x >= 0) && (x < nx) && (y >= 0) && (y < ny);
-    const bool out = ok && lane >= 1 && lane <= kStrip && row >= 1 && row <= NY - 2;
+    const bool out = x < nx && y >= 0 && y < ny && row >= 1 && row <= NY - 2;
     const int z0 = chunk * planes_per_block;
     const int z1 = min(nz, z0 + planes_per_block);
 
@@ -215,33 +291,51 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
     __shared__ float sh3[2][NY][64];
     __shared__ float sh4[2][NY][64];
 
+    // one base per array and field offsets added per load (keeps the scalar
+    // registers for the collision operator)
+    const OFF fb = (OFF)(nodes * 4);  // bytes per field
+
     struct Plane {
         float f[7], phi[3], s;
+        float h[7], hphi[3], hs;  // the node just outside the strip (left half: x0 - 1, right half: x0 + 64)
     };
     // nodes outside the box read the nearest node inside it (see the 2D kernel)
-    const int64_t xyc = (int64_t)min(max(y, 0), ny - 1) * nx + min(max(x, 0), nx - 1);
+    const int64_t yoff = (int64_t)min(max(y, 0), ny - 1) * nx;
+    const int64_t xyc = yoff + min(x, nx - 1);
+    const int64_t xyh = yoff + (lane < 32 ? max(x0 - 1, 0) : min(x0 + kStrip, nx - 1));
     auto load_at = [&](int z, Plane& p) {
-        const int64_t node = (int64_t)min(max(z, 0), nz - 1) * plane + xyc;
+        const int64_t zoff = (int64_t)min(max(z, 0), nz - 1) * plane;
+        const OFF bm = (OFF)((zoff + xyc) * 4), bh = (OFF)((zoff + xyh) * 4);
 #pragma unroll
-        for (int i = 0; i < 7; ++i) p.f[i] = fin[i * nodes + node];
+        for (int i = 0; i < 7; ++i) p.f[i] = ldf(fin, bm + i * fb);
 #pragma unroll
-        for (int mu = 0; mu < 3; ++mu) p.phi[mu] = Phi[mu * nodes + node];
-        p.s = HAS_S ? S[node] : 0.f;
+        for (int mu = 0; mu < 3; ++mu) p.phi[mu] = ldf(Phi, bm + mu * fb);
+        p.s = HAS_S ? ldf(S, bm) : 0.f;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) p.h[i] = ldf(fin, bh + i * fb);
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) p.hphi[mu] = ldf(Phi, bh + mu * fb);
+        p.hs = HAS_S ? ldf(S, bh) : 0.f;
     };
-    auto collide_at = [&](const Plane& p, float (&fs)[7]) { collide_node<7>(cc, p.f, p.phi, p.s, fs); };
+    auto collide_at = [&](const Plane& p, float (&fs)[7], float& hv) {
+        collide_node<7>(cc, p.f, p.phi, p.s, fs);
+        float h1, h2;
+        collide_two<7>(cc, p.h, p.hphi, p.hs, 1, 2, h1, h2);
+        hv = lane < 32 ? h1 : h2;
+    };
 
     Plane ring[D];
     load_at(z0 - 1, ring[D - 1]);  // halo plane below the chunk
 #pragma unroll
     for (int k = 0; k < D - 1; ++k) load_at(z0 + k, ring[k]);
-    float prev5, cur[7];
+    float prev5, cur[7], hcur;
     {
-        float t[7];
-        collide_at(ring[D - 1], t);
+        float t[7], th;
+        collide_at(ring[D - 1], t, th);
         prev5 = t[5];
     }
     load_at(z0 + D - 1, ring[D - 1]);
-    collide_at(ring[0], cur);
+    collide_at(ring[0], cur, hcur);
     for (int zb = z0; zb < z1; zb += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
@@ -250,11 +344,13 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
             sh3[par][row][lane] = cur[3];
             sh4[par][row][lane] = cur[4];
             load_at(z + D, ring[u]);
-            float nxt[7];
-            collide_at(ring[(u + 1) % D], nxt);  // plane z + 1
+            float nxt[7], hnxt;
+            collide_at(ring[(u + 1) % D], nxt, hnxt);  // plane z + 1
             lds_barrier();
-            const float from_left = __shfl_up(cur[1], 1, 64);
-            const float from_right = __shfl_down(cur[2], 1, 64);
+            const float sl = __shfl_up(cur[1], 1, 64);
+            const float sr = __shfl_down(cur[2], 1, 64);
+            const float from_left = lane == 0 ? hcur : sl;
+            const float from_right = lane == 63 ? hcur : sr;
             const float from_below = row >= 1 ? sh3[par][row - 1][lane] : 0.f;       // f*_3 of y-1
             const float from_above = row + 1 < NY ? sh4[par][row + 1][lane] : 0.f;  // f*_4 of y+1
             float f[7] = {cur[0], from_left, from_right, from_below, from_above, prev5, nxt[6]};
@@ -267,25 +363,26 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
                 else known += f[i];
             }
             if (nu > 0) {
-                const float share = (cc.c_wall - known) / (float)nu;
+                const float share = (cc.c_wall - known) * inv_count(nu);
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
                     if (unk[i]) f[i] = share;
             }
             if (out && z < z1) {
-                const int64_t node = (int64_t)z * plane + (int64_t)y * nx + x;
+                const OFF bo = (OFF)(((int64_t)z * plane + (int64_t)y * nx + x) * 4);
                 float c = 0.f;
 #pragma unroll
                 for (int i = 0; i < 7; ++i) {
-                    fout[i * nodes + node] = f[i];
+                    stv(fout, bo + i * fb, f[i]);
                     c += f[i];
                 }
-                Cout[node] = c;
-                if (PACK) Cpout[node] = pack_hilo(c);
+                stv(Cout, bo, c);
+                if (PACK) stv(Cpout, bo, pack_hilo(c));
             }
             prev5 = cur[5];
 #pragma unroll
             for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
+            hcur = hnxt;
         }
     }
 }
@@ -378,15 +475,16 @@ int collide_rows_override()
 hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
                                  const float* S, float* C_out, uint32_t* Cp_out, hipStream_t s)
 {
+    // 32-bit byte offsets while every array (at most 7 fields of the node count) fits in 4 GiB
+    const bool small = nodes_of(cc) * 7 * 4 < ((int64_t)1 << 32);
     if (cc.dim == 2) {
         const int nx = cc.n[0], ny = cc.n[1];
         const int strips = (nx + kStrip - 1) / kStrip;
-        // Rows per wavefront: short marches leave more wavefronts to hide the
-        // latency of each row's loads, long ones amortise the two halo rows.
-        // Measured best on MI355X: 4 rows up to 512 rows of grid, 16 while the
-        // state stays in the Infinity Cache (up to 4 M nodes), 8 beyond.
+        // Rows per wavefront: short marches leave more wavefronts to share the
+        // chip, long ones amortise the two halo rows.  Measured best on MI355X:
+        // 8 rows up to 512 rows of grid, 16 beyond (1024^2 and 4096^2).
         int rows = collide_rows_override();
-        if (rows <= 0) rows = ny <= 512 ? 4 : ((int64_t)nx * ny <= (1 << 22) ? 16 : 8);
+        if (rows <= 0) rows = ny <= 512 ? 8 : 16;
         const int chunks = (ny + rows - 1) / rows;
         const int waves = strips * chunks;
         const unsigned blocks = (unsigned)((waves + 3) / 4);
@@ -394,12 +492,22 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out, rows,
                                strips, waves);
         };
-        if (S) {
-            if (Cp_out) go(collide_stream_2d<true, true>);
-            else go(collide_stream_2d<true, false>);
+        if (small) {
+            if (S) {
+                if (Cp_out) go(collide_stream_2d<true, true, uint32_t>);
+                else go(collide_stream_2d<true, false, uint32_t>);
+            } else {
+                if (Cp_out) go(collide_stream_2d<false, true, uint32_t>);
+                else go(collide_stream_2d<false, false, uint32_t>);
+            }
         } else {
-            if (Cp_out) go(collide_stream_2d<false, true>);
-            else go(collide_stream_2d<false, false>);
+            if (S) {
+                if (Cp_out) go(collide_stream_2d<true, true, uint64_t>);
+                else go(collide_stream_2d<true, false, uint64_t>);
+            } else {
+                if (Cp_out) go(collide_stream_2d<false, true, uint64_t>);
+                else go(collide_stream_2d<false, false, uint64_t>);
+            }
         }
         return hipGetLastError();
     }
@@ -417,12 +525,22 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out,
                            planes, sx, sy);
     };
-    if (S) {
-        if (Cp_out) go(collide_stream_3d<NY, true, true>);
-        else go(collide_stream_3d<NY, true, false>);
+    if (small) {
+        if (S) {
+            if (Cp_out) go(collide_stream_3d<NY, true, true, uint32_t>);
+            else go(collide_stream_3d<NY, true, false, uint32_t>);
+        } else {
+            if (Cp_out) go(collide_stream_3d<NY, false, true, uint32_t>);
+            else go(collide_stream_3d<NY, false, false, uint32_t>);
+        }
     } else {
-        if (Cp_out) go(collide_stream_3d<NY, false, true>);
-        else go(collide_stream_3d<NY, false, false>);
+        if (S) {
+            if (Cp_out) go(collide_stream_3d<NY, true, true, uint64_t>);
+            else go(collide_stream_3d<NY, true, false, uint64_t>);
+        } else {
+            if (Cp_out) go(collide_stream_3d<NY, false, true, uint64_t>);
+            else go(collide_stream_3d<NY, false, false, uint64_t>);
+        }
     }
     return hipGetLastError();
 }
