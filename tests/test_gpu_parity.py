@@ -278,6 +278,34 @@ def test_full_size_sampled_step(name, precision):
     assert err <= (1e-5 if precision == "fp32" else 1e-4)
 
 
+@pytest.mark.parametrize("name", ["c4_4096sq", "c2_1024sq", "c3_256cube"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_full_size_phi_per_axis(name, precision):
+    """The fractional term at full size, per axis (per alpha), on the state after
+    20 steps: the GEMM launch of a step against the oracle's direct sums at
+    sampled nodes.  Errors are measured against sum_k |K||C| of the same node,
+    which is the oracle's Phi of |C| because every product-rule weight is
+    >= 0 (C itself changes sign after a few steps, so Phi can cancel)."""
+    cfg = synth.config(name)
+    _banner(f"full-size phi per axis {name} {precision}")
+    with _solver(cfg, precision) as s:
+        s.set_C(synth.initial_C(cfg).astype(np.float32))
+        s.step(20)
+        C = s.get_C(device=False)
+        got = s.apply_phi(None).cpu().numpy().reshape(cfg["dim"], -1)
+    nodes = _sample_nodes(cfg, 400, 11)
+    ref = oracle.phi_at(cfg, C.astype(np.float64), nodes)
+    mag = oracle.phi_at(cfg, np.abs(C).astype(np.float64), nodes)  # sum_k |K||C|
+    bound = 4 * max(cfg["n"]) * 2.0**-24 if precision == "fp32" else 2.0**-14
+    for mu in range(cfg["dim"]):
+        g, r = got[mu, nodes].astype(np.float64), ref[mu]
+        rel = np.abs(g - r) / np.maximum(mag[mu], 1e-30)
+        l2 = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+        print(f"[gpu-parity] {name} {precision} axis {mu} alpha={cfg['alpha'][mu]}: "
+              f"rel L2 {l2:.2e}, max rel {rel.max():.2e}", flush=True)
+        assert rel.max() <= bound
+
+
 def test_error_codes_on_device():
     from paper_1706_09161_amd import LbmError, _lib
 
