@@ -95,7 +95,15 @@ __global__ void broadcast_kernel(const float* __restrict__ gC, float* __restrict
 // Reverse of one step at every node (streaming + Dirichlet rule, collision,
 // equilibrium).  Writes fdir (the part of fbar^t that does not go through C),
 // Cbar (equilibrium part), Phibar, adds to dS, and per-workgroup FP64 partial
-// sums of dL/dR (Q*Q) and dL/du (d).
+// sums of
+//   the flux block of dL/dLambda: sum_x mbar_a(x) mdev_b(x), a, b < d, with
+//     mbar = M^-T fbar* (flux rows: (fbar*_{2a+1} - fbar*_{2a+2}) / 2) and
+//     mdev = M (f^eq - f) (flux rows: dev_{2b+1} - dev_{2b+2}),
+//     which is all of dL/dR = fbar* (f^eq - f)^T that reaches D
+//     (dL/dLambda = M^-T (dL/dR) M^T; only the flux block of Lambda depends on D);
+//   dL/du_mu (d values);
+//   tr dL/dR = sum_i fbar*_i (f^eq_i - f_i) (BGK: R = I / lambda).
+// Grid: x across threads, y and z across workgroups (no integer division).
 template <int Q>
 __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float* __restrict__ fbar,
                                                        const float* __restrict__ f, const float* __restrict__ Phi,
@@ -104,14 +112,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
                                                        double* __restrict__ part, int64_t nodes)
 {
     constexpr int d = (Q - 1) / 2;
-    constexpr int NV = Q * Q + d;
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NV = d * d + d + 1;
+    const int c[3] = {(int)(blockIdx.x * kBlock + threadIdx.x), (int)blockIdx.y, (int)blockIdx.z};
+    const int64_t x = ((int64_t)c[2] * ac.n[1] + c[1]) * ac.n[0] + c[0];
     double red[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[k] = 0.0;
-    if (x < nodes) {
-        int c[3];
-        coords(ac, x, c);
+    if (c[0] < ac.n[0]) {
         // adjoint of f*(x): pulled from the node each population moved to
         float fsb[Q];
 #pragma unroll
@@ -119,6 +126,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
             int y[3] = {c[0], c[1], c[2]};
             if (i > 0) y[(i - 1) / 2] += ((i - 1) & 1) ? -1 : 1;
             bool inside = true;
+#pragma unroll
             for (int mu = 0; mu < d; ++mu) inside = inside && y[mu] >= 0 && y[mu] < ac.n[mu];
             if (!inside) {
                 fsb[i] = 0.f;
@@ -129,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
             // unknown populations at y (their sources lie outside) share its Dirichlet deficit
             int cnt = 0;
             float sum = 0.f;
+#pragma unroll
             for (int b = 1; b < Q; ++b) {
                 const int mu = (b - 1) / 2;
                 const int src = y[mu] - (((b - 1) & 1) ? -1 : 1);
@@ -165,6 +174,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
         // collision reversed
         float feqbar[Q];
         float sb = 0.f;
+        double tr = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             float r = 0.f;
@@ -173,12 +183,18 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
             feqbar[i] = r;
             fdir[(int64_t)i * nodes + x] = fsb[i] - r;
             sb = fmaf(ac.wdt[i], fsb[i], sb);
+            tr += (double)fsb[i] * (double)(feq[i] - fx[i]);
         }
         dS[x] += sb;
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < d; ++a) {
+            const double mb = 0.5 * ((double)fsb[2 * a + 1] - (double)fsb[2 * a + 2]);
 #pragma unroll
-            for (int j = 0; j < Q; ++j) red[i * Q + j] = (double)fsb[i] * (double)(feq[j] - fx[j]);
+            for (int b = 0; b < d; ++b) {
+                const double md = (double)(feq[2 * b + 1] - fx[2 * b + 1]) - (double)(feq[2 * b + 2] - fx[2 * b + 2]);
+                red[a * d + b] = mb * md;
+            }
+        }
         // equilibrium reversed
         float cb = feqbar[0];
 #pragma unroll
@@ -186,11 +202,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
             const float dp = feqbar[2 * mu + 1], dm = feqbar[2 * mu + 2];
             cb = fmaf(ac.adv[mu], dp - dm, cb);
             phibar[(int64_t)mu * nodes + x] = -ac.w[0] * feqbar[0] + ac.w[2 * mu + 1] * (dp + dm);
-            red[Q * Q + mu] = (double)ac.uscale * (double)C * (double)(dp - dm);
+            red[d * d + mu] = (double)ac.uscale * (double)C * (double)(dp - dm);
         }
+        red[d * d + d] = tr;
         cbar[x] = cb;
     }
-    block_sum_store<NV>(red, part + (int64_t)blockIdx.x * NV);
+    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum_store<NV>(red, part + blk * NV);
 }
 
 // Reverse of the initial equilibrium f^0 = f^eq(C0', Phi(C0')): fbar^0 is the
@@ -254,6 +272,30 @@ __global__ __launch_bounds__(kBlock) void reduce_partials(const double* __restri
     if (threadIdx.x == 0) acc[off + v] += sh[0];
 }
 
+// fbar_i = fdir_i + Cbar + sum_mu (K_mu^T Phibar_mu), and per-workgroup FP64
+// partial sums of <Phibar_mu, (dK_mu/dp_mu) C> (psi = (dK/dp) C)
+template <int D>
+__global__ __launch_bounds__(kBlock) void combine_dot(const float* __restrict__ fdir, const float* __restrict__ cbar,
+                                                      const float* __restrict__ kt, const float* __restrict__ phibar,
+                                                      const float* __restrict__ psi, float* __restrict__ fbar, int Q,
+                                                      double* __restrict__ part, int64_t nodes)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double red[D];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) red[mu] = 0.0;
+    if (x < nodes) {
+        float c = cbar[x];
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            c += kt[mu * nodes + x];
+            red[mu] = (double)phibar[mu * nodes + x] * (double)psi[mu * nodes + x];
+        }
+        for (int i = 0; i < Q; ++i) fbar[i * nodes + x] = fdir[i * nodes + x] + c;
+    }
+    block_sum_store<D>(red, part + (int64_t)blockIdx.x * D);
+}
+
 // fbar_i = fdir_i + Cbar + sum_mu (K_mu^T Phibar_mu)
 __global__ void combine_kernel(const float* __restrict__ fdir, const float* __restrict__ cbar,
                                const float* __restrict__ kt, float* __restrict__ fbar, int Q, int d, int64_t nodes)
@@ -297,7 +339,8 @@ struct AdjointState {
     float* kt = nullptr;
     float* psi = nullptr;
     float* dS = nullptr;
-    double* part = nullptr;
+    double* part = nullptr;   // per-workgroup partial sums of adjoint_node
+    double* part2 = nullptr;  // per-workgroup partial sums of the p-gradient
     double* acc = nullptr;
     void* opmem = nullptr;
     AxisOp opsT[3], opsP[3];
@@ -307,7 +350,7 @@ void adjoint_free(AdjointState* a)
 {
     if (!a) return;
     void* ptrs[] = {a->ckpt, a->seg_f, a->seg_phi, a->seg_C, a->fbar, a->fdir, a->cbar,
-                    a->phibar, a->kt, a->psi, a->dS, a->part, a->acc, a->opmem};
+                    a->phibar, a->kt, a->psi, a->dS, a->part, a->part2, a->acc, a->opmem};
     for (void* p : ptrs) (void)hipFree(p);
     delete a;
 }
@@ -383,6 +426,13 @@ bool build_ops(lbm_fade* h, AdjointState* A)
     return hipMemcpy(A->opmem, host.data(), bytes, hipMemcpyHostToDevice) == hipSuccess;
 }
 
+// workgroups of the adjoint_node grid (x across threads, y and z across workgroups)
+int64_t nb_node_max(const lbm_fade* h)
+{
+    const int64_t gx = (h->grid.n[0] + kBlock - 1) / kBlock;
+    return gx * h->grid.n[1] * (h->dim == 3 ? h->grid.n[2] : 1);
+}
+
 bool alloc_state(lbm_fade* h, AdjointState* A, int64_t n, int K)
 {
     const int64_t nodes = h->nodes;
@@ -407,7 +457,8 @@ bool alloc_state(lbm_fade* h, AdjointState* A, int64_t n, int K)
             hipMalloc(&A->kt, sizeof(float) * d * nodes) != hipSuccess ||
             hipMalloc(&A->psi, sizeof(float) * d * nodes) != hipSuccess ||
             hipMalloc(&A->dS, sizeof(float) * nodes) != hipSuccess ||
-            hipMalloc(&A->part, sizeof(double) * nb * (kMaxQ * kMaxQ + 3)) != hipSuccess ||
+            hipMalloc(&A->part, sizeof(double) * nb_node_max(h) * (3 * 3 + 3 + 1)) != hipSuccess ||
+            hipMalloc(&A->part2, sizeof(double) * nb * 3) != hipSuccess ||
             hipMalloc(&A->acc, sizeof(double) * 64) != hipSuccess)
             return false;
     }
@@ -462,7 +513,29 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     for (int i = 0; i < Q; ++i) ac.wdt[i] = h->cc.wSdt[i];
 
     const int64_t nb = (nodes + kBlock - 1) / kBlock;
-    const int NV = Q * Q + d;
+    const int NV = d * d + d + 1;  // flux block of dL/dLambda, dL/du, tr dL/dR
+    const dim3 node_grid((unsigned)((ac.n[0] + kBlock - 1) / kBlock), (unsigned)ac.n[1], (unsigned)(d == 3 ? ac.n[2] : 1));
+    const int64_t nb_node = (int64_t)node_grid.x * node_grid.y * node_grid.z;
+    // the two operators of the reversed fractional term of every axis, one launch:
+    // K^T Phibar (into kt) and (dK/dp) C (into psi)
+    AxisOp ops2[2 * 3];
+    AxisLayout lays2[2 * 3];
+    for (int mu = 0; mu < d; ++mu) {
+        ops2[mu] = A->opsT[mu];
+        ops2[d + mu] = A->opsP[mu];
+        lays2[mu] = lays2[d + mu] = h->lays[mu];
+    }
+    auto reversed_phi = [&](const float* Cin) -> hipError_t {
+        const float* in[2 * 3];
+        float* outp[2 * 3];
+        for (int mu = 0; mu < d; ++mu) {
+            in[mu] = A->phibar + (int64_t)mu * nodes;
+            outp[mu] = A->kt + (int64_t)mu * nodes;
+            in[d + mu] = Cin;
+            outp[d + mu] = A->psi + (int64_t)mu * nodes;
+        }
+        return launch_fractional_ops(ops2, lays2, in, outp, 2 * d, s);
+    };
     const size_t fq = sizeof(float) * Q * nodes;
     const int64_t nseg = (n + K - 1) / K;
     float* gCdev = nullptr;
@@ -487,7 +560,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     ADJ_TRY(hipMemsetAsync(A->dS, 0, sizeof(float) * nodes, s));
     hipLaunchKernelGGL(broadcast_kernel, dim3(nblk(nodes)), dim3(kBlock), 0, s, gC, A->fbar, Q, nodes);
     ADJ_TRY(hipGetLastError());
-    const int offU = Q * Q, offP = Q * Q + d;
+    const int offU = d * d, offTr = d * d + d, offP = d * d + d + 1;
     for (int64_t sg = nseg - 1; sg >= 0; --sg) {
         const int64_t t0 = sg * K;
         const int len = (int)((t0 + K <= n ? t0 + K : n) - t0);
@@ -509,24 +582,24 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
             const float* phi_j = A->seg_phi + (int64_t)j * d * nodes;
             const float* C_j = A->seg_C + (int64_t)j * nodes;
             if (Q == 5)
-                hipLaunchKernelGGL(adjoint_node<5>, dim3(nblk(nodes)), dim3(kBlock), 0, s, ac, A->fbar, f_at(j), phi_j,
-                                   A->fdir, A->cbar, A->phibar, A->dS, A->part, nodes);
+                hipLaunchKernelGGL(adjoint_node<5>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_at(j), phi_j, A->fdir,
+                                   A->cbar, A->phibar, A->dS, A->part, nodes);
             else
-                hipLaunchKernelGGL(adjoint_node<7>, dim3(nblk(nodes)), dim3(kBlock), 0, s, ac, A->fbar, f_at(j), phi_j,
-                                   A->fdir, A->cbar, A->phibar, A->dS, A->part, nodes);
+                hipLaunchKernelGGL(adjoint_node<7>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_at(j), phi_j, A->fdir,
+                                   A->cbar, A->phibar, A->dS, A->part, nodes);
             ADJ_TRY(hipGetLastError());
-            hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb, NV, A->acc, 0);
+            hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb_node, NV, A->acc, 0);
             ADJ_TRY(hipGetLastError());
-            // fractional term reversed: K^T Phibar, and <Phibar, dK/dp C>
-            ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nullptr, nodes, A->kt, nodes, s));
-            ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C_j, nullptr, 0, A->psi, nodes, s));
-            if (d == 2) hipLaunchKernelGGL(dot_axes<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
-            else hipLaunchKernelGGL(dot_axes<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
+            // fractional term reversed: K^T Phibar, and (dK/dp) C for <Phibar, dK/dp C>
+            ADJ_TRY(reversed_phi(C_j));
+            if (d == 2)
+                hipLaunchKernelGGL(combine_dot<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->fdir, A->cbar, A->kt,
+                                   A->phibar, A->psi, A->fbar, Q, A->part2, nodes);
+            else
+                hipLaunchKernelGGL(combine_dot<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->fdir, A->cbar, A->kt,
+                                   A->phibar, A->psi, A->fbar, Q, A->part2, nodes);
             ADJ_TRY(hipGetLastError());
-            hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part, nb, d, A->acc, offP);
-            ADJ_TRY(hipGetLastError());
-            hipLaunchKernelGGL(combine_kernel, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->fdir, A->cbar, A->kt, A->fbar, Q,
-                               d, nodes);
+            hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part2, nb, d, A->acc, offP);
             ADJ_TRY(hipGetLastError());
         }
     }
@@ -542,8 +615,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     ADJ_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part, nb, d, A->acc, offU);
     ADJ_TRY(hipGetLastError());
-    ADJ_TRY(launch_fractional(A->opsT, h->lays, d, 0, A->phibar, nullptr, nodes, A->kt, nodes, s));
-    ADJ_TRY(launch_fractional(A->opsP, h->lays, d, 0, C0p, nullptr, 0, A->psi, nodes, s));
+    ADJ_TRY(reversed_phi(C0p));
     if (d == 2) hipLaunchKernelGGL(dot_axes<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
     else hipLaunchKernelGGL(dot_axes<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
     ADJ_TRY(hipGetLastError());
@@ -569,57 +641,17 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     double G[9] = {0};
     if (h->params.collision == LBM_BGK) {
         // R = I / lambda: dL/dlambda = -tr(dL/dR) / lambda^2
-        double tr = 0.0;
-        for (int i = 0; i < Q; ++i) tr += acc[i * Q + i];
+        const double tr = acc[offTr];
         const double lam = h->lam_bar[0];
         const double dlam = -tr / (lam * lam);
         for (int a = 0; a < d; ++a) G[a * d + a] = dlam * scale / d;
     } else {
-        // R = M^-1 Lambda M  =>  dL/dLambda = M^-T (dL/dR) M^T; the flux block of
-        // Lambda is B = lambda-bar^-1, dL/dlambda-bar = -B^T (dL/dB) B^T
-        double M[49] = {0};
-        for (int i = 0; i < Q; ++i) M[i] = 1.0;
-        for (int mu = 0; mu < d; ++mu) {
-            M[(1 + mu) * Q + 2 * mu + 1] = 1.0;
-            M[(1 + mu) * Q + 2 * mu + 2] = -1.0;
-        }
-        if (d == 2) {
-            const double r3[5] = {4, -1, -1, -1, -1}, r4[5] = {0, 1, 1, -1, -1};
-            for (int i = 0; i < 5; ++i) {
-                M[3 * Q + i] = r3[i];
-                M[4 * Q + i] = r4[i];
-            }
-        } else {
-            const double r4[7] = {6, -1, -1, -1, -1, -1, -1}, r5[7] = {0, 2, 2, -1, -1, -1, -1},
-                         r6[7] = {0, 0, 0, 1, 1, -1, -1};
-            for (int i = 0; i < 7; ++i) {
-                M[4 * Q + i] = r4[i];
-                M[5 * Q + i] = r5[i];
-                M[6 * Q + i] = r6[i];
-            }
-        }
-        double rn[7];
-        for (int r = 0; r < Q; ++r) {
-            rn[r] = 0;
-            for (int c = 0; c < Q; ++c) rn[r] += M[r * Q + c] * M[r * Q + c];
-        }
-        // M^-1 = M^T diag(1/rn)  =>  M^-T = diag(1/rn) M
-        double T1[49], Lb[49];
-        for (int r = 0; r < Q; ++r)
-            for (int c = 0; c < Q; ++c) {
-                double sum = 0;
-                for (int k = 0; k < Q; ++k) sum += (M[r * Q + k] / rn[r]) * acc[k * Q + c];
-                T1[r * Q + c] = sum;
-            }
-        for (int r = 0; r < Q; ++r)
-            for (int c = 0; c < Q; ++c) {
-                double sum = 0;
-                for (int k = 0; k < Q; ++k) sum += T1[r * Q + k] * M[c * Q + k];
-                Lb[r * Q + c] = sum;
-            }
+        // R = M^-1 Lambda M  =>  dL/dLambda = M^-T (dL/dR) M^T; its flux block
+        // (summed on the device) is dL/dB for B = lambda-bar^-1, and
+        // dL/dlambda-bar = -B^T (dL/dB) B^T
         double Bbar[9], BtBbar[9];
         for (int a = 0; a < d; ++a)
-            for (int b = 0; b < d; ++b) Bbar[a * d + b] = Lb[(1 + a) * Q + 1 + b];
+            for (int b = 0; b < d; ++b) Bbar[a * d + b] = acc[a * d + b];
         const double* B = h->lam_inv;
         for (int a = 0; a < d; ++a)
             for (int b = 0; b < d; ++b) {

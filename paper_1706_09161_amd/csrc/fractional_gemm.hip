@@ -739,9 +739,9 @@ __global__ __launch_bounds__(kThreads, 2) void fractional_f32_ring(FracLaunch L)
     while (axis + 1 < L.naxes && bid >= L.first[axis + 1]) ++axis;
     const int local = bid - L.first[axis];
     const int total = L.first[axis + 1] - L.first[axis];
-    if (axis == 0)
-        f32_ring_tile<true, NBJ, WL, KSPLIT, P, KFULL>(L.op[0], L.lay[0], L.C[0], L.Phi[0], L.tiles_m[0], L.tiles_n[0],
-                                                       local, total, smem_r);
+    if (L.lay[axis].contiguous)
+        f32_ring_tile<true, NBJ, WL, KSPLIT, P, KFULL>(L.op[axis], L.lay[axis], L.C[axis], L.Phi[axis],
+                                                       L.tiles_m[axis], L.tiles_n[axis], local, total, smem_r);
     else
         f32_ring_tile<false, NBJ, WL, KSPLIT, P, KFULL>(L.op[axis], L.lay[axis], L.C[axis], L.Phi[axis],
                                                         L.tiles_m[axis], L.tiles_n[axis], local, total, smem_r);
@@ -795,6 +795,10 @@ hipError_t run_f32_ring(FracLaunch& L, hipStream_t s)
 
 }  // namespace
 
+namespace {
+hipError_t run_f32_auto(FracLaunch& L, hipStream_t s);
+}
+
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
                              const uint32_t* Cp, int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s)
 {
@@ -825,6 +829,29 @@ hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxe
         if (!Cp) return hipErrorInvalidValue;
         return launch_fractional_bf16x3(L, s);
     }
+    return run_f32_auto(L, s);
+}
+
+hipError_t launch_fractional_ops(const AxisOp* ops, const AxisLayout* lays, const float* const* C, float* const* Phi,
+                                 int nops, hipStream_t s)
+{
+    if (nops < 1 || nops > kMaxOps) return hipErrorInvalidValue;
+    FracLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.naxes = nops;
+    for (int a = 0; a < nops; ++a) {
+        L.op[a] = ops[a];
+        L.lay[a] = lays[a];
+        L.C[a] = C[a];
+        L.Phi[a] = Phi[a];
+    }
+    return run_f32_auto(L, s);
+}
+
+namespace {
+
+hipError_t run_f32_auto(FracLaunch& L, hipStream_t s)
+{
     // Tile configuration: LBM_FP32_TILE (read once) selects one explicitly, for
     // tuning; by default the work is counted in 128 x 128 output tiles and
     // grids below ~2 such tiles per CU use the small split-K tiles.
@@ -866,6 +893,8 @@ hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxe
     if (grid >= 512 && (kgroups + 1) / 2 <= 128) return run_f32_ring<4, 2, 2, 2>(L, s);
     return run_f32_ring<4, 1, 4, 2>(L, s);
 }
+
+}  // namespace
 
 int64_t big_tiles(const FracLaunch& L)
 {

@@ -56,17 +56,19 @@ struct AxisLayout {
     int batches;           // strided case
 };
 
-// One launch of the fractional term for all axes of a step (workgroup ids
-// are split into per-axis ranges, axis 0 first).
+// One launch of the fractional term for all axes of a step, or for several
+// operators at once (the adjoint applies two per axis): workgroup ids are split
+// into per-operator ranges, in order.
+constexpr int kMaxOps = 6;
 struct FracLaunch {
-    AxisOp op[3];
-    AxisLayout lay[3];
-    int tiles_m[3], tiles_n[3];
-    int first[4];  // first workgroup id of every axis, first[naxes] = grid size
-    const float* C[3];      // input field of every axis
-    const uint32_t* Cp[3];  // the same fields split into BF16 (hi | lo << 16) (split-BF16 path)
-    float* Phi[3];
-    int naxes;
+    AxisOp op[kMaxOps];
+    AxisLayout lay[kMaxOps];
+    int tiles_m[kMaxOps], tiles_n[kMaxOps];
+    int first[kMaxOps + 1];  // first workgroup id of every operator, first[naxes] = grid size
+    const float* C[kMaxOps];      // input field of every operator
+    const uint32_t* Cp[kMaxOps];  // the same fields split into BF16 (hi | lo << 16) (split-BF16 path)
+    float* Phi[kMaxOps];
+    int naxes;  // operators in this launch
 };
 
 // Constants of the fused collide-stream kernel (Sec. 2.2-2.5).
@@ -86,6 +88,10 @@ struct CollideConsts {
 // (precision 1) also reads Cp, the same fields packed by launch_pack_bf16.
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
                              const uint32_t* Cp, int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s);
+// FP32 only: nops (<= kMaxOps) operators with their own layouts, inputs and
+// outputs, in one launch.
+hipError_t launch_fractional_ops(const AxisOp* ops, const AxisLayout* lays, const float* const* C, float* const* Phi,
+                                 int nops, hipStream_t s);
 // Cp[x] = bf16(C[x]) | bf16(C[x] - bf16(C[x])) << 16 (round to nearest even).
 hipError_t launch_pack_bf16(const float* C, uint32_t* Cp, int64_t count, hipStream_t s);
 // C_out receives the new moment; Cp_out (nullable) also its packed BF16 split.
