@@ -62,8 +62,9 @@ __device__ inline bool on_wall(const AdjConsts& a, const int c[3])
     return w;
 }
 
-// Sum `v` over the workgroup in FP64 (fixed order) and return it in thread 0.
-template <int NV>
+// Sum `v` over the workgroup in FP64 (fixed order) into out[0..NV): stored, or
+// (ACC) added to what the slot holds (the workgroup's running sum over steps).
+template <int NV, bool ACC = false>
 __device__ inline void block_sum_store(double (&v)[NV], double* __restrict__ out)
 {
     __shared__ double sh[kBlock / 64][NV];
@@ -79,7 +80,7 @@ __device__ inline void block_sum_store(double (&v)[NV], double* __restrict__ out
     for (int k = threadIdx.x; k < NV; k += kBlock) {
         double s = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) s += sh[w][k];
-        out[k] = s;
+        out[k] = ACC ? out[k] + s : s;
     }
 }
 
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
         cbar[x] = cb;
     }
     const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum_store<NV>(red, part + blk * NV);
+    block_sum_store<NV, true>(red, part + blk * NV);  // running sum over the reverse sweep
 }
 
 // Reverse of the initial equilibrium f^0 = f^eq(C0', Phi(C0')): fbar^0 is the
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void combine_dot(const float* __restrict__ 
         }
         for (int i = 0; i < Q; ++i) fbar[i * nodes + x] = fdir[i * nodes + x] + c;
     }
-    block_sum_store<D>(red, part + (int64_t)blockIdx.x * D);
+    block_sum_store<D, true>(red, part + (int64_t)blockIdx.x * D);  // running sum over the reverse sweep
 }
 
 // fbar_i = fdir_i + Cbar + sum_mu (K_mu^T Phibar_mu)
@@ -558,6 +559,10 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     // --- reverse sweep
     ADJ_TRY(hipMemsetAsync(A->acc, 0, sizeof(double) * 64, s));
     ADJ_TRY(hipMemsetAsync(A->dS, 0, sizeof(float) * nodes, s));
+    // per-workgroup running sums of the scalar gradients over the sweep
+    // (each workgroup adds its steps in order; one fixed-order reduction at the end)
+    ADJ_TRY(hipMemsetAsync(A->part, 0, sizeof(double) * nb_node * NV, s));
+    ADJ_TRY(hipMemsetAsync(A->part2, 0, sizeof(double) * nb * d, s));
     hipLaunchKernelGGL(broadcast_kernel, dim3(nblk(nodes)), dim3(kBlock), 0, s, gC, A->fbar, Q, nodes);
     ADJ_TRY(hipGetLastError());
     const int offU = d * d, offTr = d * d + d, offP = d * d + d + 1;
@@ -588,8 +593,6 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
                 hipLaunchKernelGGL(adjoint_node<7>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_at(j), phi_j, A->fdir,
                                    A->cbar, A->phibar, A->dS, A->part, nodes);
             ADJ_TRY(hipGetLastError());
-            hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb_node, NV, A->acc, 0);
-            ADJ_TRY(hipGetLastError());
             // fractional term reversed: K^T Phibar, and (dK/dp) C for <Phibar, dK/dp C>
             ADJ_TRY(reversed_phi(C_j));
             if (d == 2)
@@ -599,10 +602,12 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
                 hipLaunchKernelGGL(combine_dot<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->fdir, A->cbar, A->kt,
                                    A->phibar, A->psi, A->fbar, Q, A->part2, nodes);
             ADJ_TRY(hipGetLastError());
-            hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part2, nb, d, A->acc, offP);
-            ADJ_TRY(hipGetLastError());
         }
     }
+    hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb_node, NV, A->acc, 0);
+    ADJ_TRY(hipGetLastError());
+    hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part2, nb, d, A->acc, offP);
+    ADJ_TRY(hipGetLastError());
     // --- reverse of the initial equilibrium (C0' = C of the initial state)
     float* C0p = A->seg_C;  // segment 0 left C^0 in slot 0 (or compute it when n == 0)
     if (n == 0) ADJ_TRY(launch_moment(h->cc, A->ckpt, C0p, s));

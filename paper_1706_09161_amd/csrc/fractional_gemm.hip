@@ -642,7 +642,12 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
         }
     }
 
-    int c_lo = 0, c_hi = NBJ;
+    // The output of a wavefront is NBJ blocks x 4 groups of 4 rows ("units",
+    // u = 4 c + r4).  With k split across waves, the partial tiles are summed
+    // through LDS and the units are dealt out to the KSPLIT wavefronts.
+    constexpr int U = 4 * NBJ;
+    static_assert(U % KSPLIT == 0, "units divide among the k shares");
+    int u_lo = 0, u_hi = U;
     if constexpr (KSPLIT > 1) {
         __syncthreads();  // every wavefront is done with the window
         float* red = win;
@@ -654,13 +659,14 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
                 *reinterpret_cast<float4*>(red + (((wave * NBJ + c) * 4 + r4) * 64 + lane) * 4) = v;
             }
         __syncthreads();
-        c_lo = wk * (NBJ / KSPLIT);
-        c_hi = c_lo + NBJ / KSPLIT;
+        u_lo = wk * (U / KSPLIT);
+        u_hi = u_lo + U / KSPLIT;
 #pragma unroll
-        for (int c = 0; c < NBJ; ++c) {
-            if (c < c_lo || c >= c_hi) continue;
+        for (int c = 0; c < NBJ; ++c)
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
+                const int u = 4 * c + r4;
+                if (u < u_lo || u >= u_hi) continue;
                 float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                 for (int s = 0; s < KSPLIT; ++s) {
@@ -676,42 +682,41 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
                 acc[c][4 * r4 + 2] = sum.z;
                 acc[c][4 * r4 + 3] = sum.w;
             }
-        }
     }
 
     // epilogue: boundary columns (rank-2 correction) and stores
     if constexpr (CONTIG) {
-        float cb0[16], cbN[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int tl = 32 * wl + 8 * (r >> 2) + 4 * lh + (r & 3);
-            cb0[r] = w0s[tl];
-            cbN[r] = wNs[tl];
-        }
+        // rows = lines (8 r4 + 4 lh + e), columns = outputs j0 + 32 c + li
 #pragma unroll
         for (int c = 0; c < NBJ; ++c) {
-            if (c < c_lo || c >= c_hi) continue;
             const int jl = 32 * c + li, j = j0 + jl;
             const float k0 = c0s[jl], kN = cNs[jl];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t line = line0 + 8 * (r >> 2) + 4 * lh + (r & 3);
-                if (line < lines && j < n) {
-                    float v = acc[c][r];
-                    v = fmaf(k0, cb0[r], v);
-                    v = fmaf(kN, cbN[r], v);
-                    Pb[line * n + j] = v;
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int u = 4 * c + r4;
+                if (u < u_lo || u >= u_hi) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int tl = 32 * wl + 8 * r4 + 4 * lh + e;
+                    const int64_t line = (int64_t)lt * LT + tl;
+                    if (line < lines && j < n) {
+                        float v = acc[c][4 * r4 + e];
+                        v = fmaf(k0, w0s[tl], v);
+                        v = fmaf(kN, wNs[tl], v);
+                        Pb[line * n + j] = v;
+                    }
                 }
             }
         }
     } else {
         const int64_t line = line0 + li;
 #pragma unroll
-        for (int c = 0; c < NBJ; ++c) {
-            if (c < c_lo || c >= c_hi) continue;
+        for (int c = 0; c < NBJ; ++c)
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
-                const int jl0 = 32 * c + 8 * r4 + 4 * lh;
+                const int u = 4 * c + r4;
+                if (u < u_lo || u >= u_hi) continue;
+                const int jl0 = 32 * c + 8 * r4 + 4 * lh;  // 4 consecutive outputs
                 const float4 k0 = *reinterpret_cast<const float4*>(c0s + jl0);
                 const float4 kN = *reinterpret_cast<const float4*>(cNs + jl0);
                 const float k0v[4] = {k0.x, k0.y, k0.z, k0.w}, kNv[4] = {kN.x, kN.y, kN.z, kN.w};
@@ -726,7 +731,6 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
                     }
                 }
             }
-        }
     }
 }
 
@@ -868,6 +872,8 @@ hipError_t run_f32_auto(FracLaunch& L, hipStream_t s)
     case 10: return run_f32_ring<8, 1, 4, 2>(L, s);
     case 11: return run_f32_ring<8, 2, 2, 2>(L, s);
     case 12: return run_f32_ring<8, 4, 1, 2>(L, s);
+    case 13: return run_f32_ring<2, 1, 4, 2>(L, s);
+    case 14: return run_f32_ring<2, 2, 2, 2>(L, s);
     default: break;
     }
     // Register-direct kernel.  Output tiles of 256 when every axis fits in
@@ -891,7 +897,10 @@ hipError_t run_f32_auto(FracLaunch& L, hipStream_t s)
     if (grid >= 512 && kgroups <= 128) return run_f32_ring<4, 4, 1, 2>(L, s);
     f32_ring_grid<4, 2, 2>(T, grid, lds);
     if (grid >= 512 && (kgroups + 1) / 2 <= 128) return run_f32_ring<4, 2, 2, 2>(L, s);
-    return run_f32_ring<4, 1, 4, 2>(L, s);
+    f32_ring_grid<4, 1, 4>(T, grid, lds);
+    if (grid >= 256) return run_f32_ring<4, 1, 4, 2>(L, s);
+    // small grids: output tiles of 64 so that every CU gets a workgroup
+    return run_f32_ring<2, 1, 4, 2>(L, s);
 }
 
 }  // namespace
@@ -909,11 +918,11 @@ int64_t big_tiles(const FracLaunch& L)
 
 int tile_choice(const char* var)
 {
-    // 0 = automatic; 1..12 = the explicit configurations listed at the call sites
+    // 0 = automatic; 1..14 = the explicit configurations listed at the call sites
     const char* v = getenv(var);
     if (!v || !*v) return 0;
     const int c = atoi(v);
-    return (c >= 1 && c <= 12) ? c : 0;
+    return (c >= 1 && c <= 14) ? c : 0;
 }
 
 }  // namespace lbm

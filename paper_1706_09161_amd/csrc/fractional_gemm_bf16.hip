@@ -392,6 +392,7 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
                                                  int tiles_l, int tiles_j, int bid, int total, unsigned char* smem)
 {
     static_assert(WL * KSPLIT == kWaves, "4 wavefronts per workgroup");
+    static_assert(NBJ % KSPLIT == 0, "output blocks divide among the k shares");
     constexpr int R = 2 * NBJ;  // Toeplitz ring period (steps)
     static_assert(R % P == 0, "prefetch depth divides the ring period");
     constexpr int JT = 32 * NBJ;  // outputs per tile
