@@ -335,6 +335,65 @@ int forward_step(lbm_fade* h, hipStream_t s)
     return LBM_OK;
 }
 
+// ---- step graph: kGraphSteps steps (an even number, so the population
+// buffers end where they started) captured once per handle and replayed with
+// one launch.  Kernels only (no memset or copy nodes).
+constexpr int kGraphSteps = 10;
+
+bool graphs_enabled()
+{
+    const char* v = getenv("LBM_STEP_GRAPH");
+    return !(v && v[0] == '0');
+}
+
+void graph_key(int (&k)[3])
+{
+    k[0] = lbm::tile_choice("LBM_FP32_TILE");
+    k[1] = lbm::tile_choice("LBM_BF16_TILE");
+    const char* r = getenv("LBM_COLLIDE_ROWS");
+    k[2] = r ? atoi(r) : 0;
+}
+
+void drop_graph(lbm_fade* h)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+}
+
+int build_step_graph(lbm_fade* h)
+{
+    drop_graph(h);
+    if (!h->gstream) HIP_TRY(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    const int cur0 = h->cur;
+    const int64_t done0 = h->steps_done;
+    const bool init0 = h->at_initial_C;
+    HIP_TRY(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeRelaxed));
+    int rc = LBM_OK;
+    for (int k = 0; k < kGraphSteps && rc == LBM_OK; ++k) rc = forward_step(h, h->gstream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->gstream, &g);
+    h->cur = cur0;  // capturing ran nothing
+    h->steps_done = done0;
+    h->at_initial_C = init0;
+    if (rc != LBM_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != LBM_OK ? rc : fail(LBM_EDEVICE, std::string("step graph capture: ") + hipGetErrorString(e));
+    }
+    const hipError_t e2 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        h->gexec = nullptr;
+        return fail(LBM_EDEVICE, std::string("step graph instantiation: ") + hipGetErrorString(e2));
+    }
+    h->graph = g;
+    h->gcur = cur0;
+    h->gS = h->S;
+    graph_key(h->gkey);
+    return LBM_OK;
+}
+
 // C := sum_i f_i of the current populations (and its BF16 split)
 int refresh_C(lbm_fade* h, hipStream_t s)
 {
@@ -529,6 +588,8 @@ void lbm_fade_destroy(lbm_fade_t h)
 {
     if (!h) return;
     (void)hipDeviceSynchronize();
+    drop_graph(h);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
     lbm::adjoint_free(h->adj);
     (void)hipFree(h->f[0]);
     (void)hipFree(h->f[1]);
@@ -594,6 +655,24 @@ int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream)
     if (rc) return rc;
     hipStream_t s = as_stream(stream);
     const int every = h->params.nonfinite_check_every;
+    if (every == 0 && n >= kGraphSteps && graphs_enabled()) {
+        int key[3];
+        graph_key(key);
+        if (!h->gexec || h->gS != h->S || key[0] != h->gkey[0] || key[1] != h->gkey[1] || key[2] != h->gkey[2]) {
+            rc = build_step_graph(h);
+            if (rc) return rc;
+        }
+        if (h->cur != h->gcur) {  // one direct step puts the populations where the graph starts
+            rc = forward_step(h, s);
+            if (rc) return rc;
+            --n;
+        }
+        for (; n >= kGraphSteps; n -= kGraphSteps) {
+            HIP_TRY(hipGraphLaunch(h->gexec, s));
+            h->steps_done += kGraphSteps;
+            h->at_initial_C = false;
+        }
+    }
     for (int64_t m = 0; m < n; ++m) {
         rc = forward_step(h, s);
         if (rc) return rc;

@@ -37,6 +37,13 @@ struct lbm_fade {
     double lam_inv[9] = {0};  // lambda-bar^-1 (flux block of Lambda)
     double e2 = 0, w0 = 0, wi = 0;
     lbm::AdjointState* adj = nullptr;
+    // step graph: a fixed number of steps captured once and replayed
+    hipStream_t gstream = nullptr;  // capture stream (default priority)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gcur = 0;                   // f[gcur] holds the populations the graph starts from
+    const float* gS = nullptr;      // source pointer the graph was captured with
+    int gkey[3] = {0, 0, 0};        // tuning variables at capture (FP32 tile, BF16 tile, collide rows)
 };
 
 namespace lbm {

@@ -306,6 +306,35 @@ def test_full_size_phi_per_axis(name, precision):
         assert rel.max() <= bound
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_step_graph_matches_direct_launches(precision, monkeypatch):
+    """lbm_fade_step replays a captured graph of 10 steps: every replay, with
+    eager work (copies, apply_phi, a changed source) between replays, must give
+    bitwise the populations of direct launches."""
+    cfg = synth.small(2, [160, 96], alpha=[1.4, 1.7], p=[0.3, 0.8], seed=35, with_source=True)
+    C0 = synth.initial_C(cfg).astype(np.float32)
+    S = synth.source(cfg).astype(np.float32)
+
+    def run(graph: bool):
+        monkeypatch.setenv("LBM_STEP_GRAPH", "1" if graph else "0")
+        out = []
+        with _solver(cfg, precision) as s:
+            s.set_C(C0)
+            for n in (25, 13, 30, 10, 21):
+                s.step(n)
+                out.append(s.get_f(device=False))
+                out.append(s.apply_phi(None).cpu().numpy())
+                if n == 13:
+                    s.set_source(S)  # the graph is captured again with the source
+                if n == 10:
+                    s.set_source(2 * S)  # same buffer, new values
+        return out
+
+    direct, graph = run(False), run(True)
+    for k, (a, b) in enumerate(zip(direct, graph)):
+        assert np.array_equal(a, b), k
+
+
 def test_error_codes_on_device():
     from paper_1706_09161_amd import LbmError, _lib
 
