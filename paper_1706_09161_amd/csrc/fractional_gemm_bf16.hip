@@ -742,7 +742,7 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
 }
 
 template <int NBJ, int WL, int KSPLIT, int P, bool VEC_X, bool KFULL>
-__global__ __launch_bounds__(kThreads) void fractional_bf16x3_ring(FracLaunch L)
+__global__ __launch_bounds__(kThreads, NBJ <= 4 ? 2 : 1) void fractional_bf16x3_ring(FracLaunch L)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_r[];
     const int bid = blockIdx.x;
@@ -826,19 +826,21 @@ hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s)
     case 10: return run_ring<8, 1, 4, 8>(L, s);
     case 11: return run_ring<8, 2, 2, 8>(L, s);
     case 12: return run_ring<8, 4, 1, 8>(L, s);
+    case 13: return run_ring<4, 1, 4, 4>(L, s);
+    case 14: return run_ring<4, 2, 2, 4>(L, s);
     default: break;
     }
-    // Register-ring kernel; the k loop is split across the wavefronts of a
-    // workgroup when there are too few (32 x 256)-output tiles to fill the chip.
+    // Register-ring kernel: wavefront tiles of 32 x 256 outputs, 4 line blocks
+    // per workgroup, when that gives >= 512 workgroups; otherwise tiles of
+    // 32 x 128 (two workgroups per CU) with k split 4 ways (measured best at
+    // 512^2 and 1024^2).
     {
         FracLaunch T = L;
         int64_t grid = 0;
         size_t lds = 0;
         ring_grid<8, 4, 1>(T, grid, lds);
         if (grid >= 512) return run_ring<8, 4, 1, 4>(L, s);
-        ring_grid<8, 2, 2>(T, grid, lds);
-        if (grid >= 256) return run_ring<8, 2, 2, 4>(L, s);
-        return run_ring<8, 1, 4, 4>(L, s);
+        return run_ring<4, 1, 4, 4>(L, s);
     }
 }
 
