@@ -79,7 +79,9 @@ def lib():
             "fo_collide_node": (ctypes.c_int, [P, dp, ctypes.c_double, dp, ctypes.c_double, dp]),
             "fo_moment": (ctypes.c_int, [P, dp, dp]),
             "fo_init": (ctypes.c_int, [P, dp, dp]),
+            "fo_init_var": (ctypes.c_int, [P, dp, dp, dp]),
             "fo_step": (ctypes.c_int, [P, dp, dp, ctypes.c_int64]),
+            "fo_step_var": (ctypes.c_int, [P, dp, dp, dp, dp, ctypes.c_int64]),
             "fo_step_sampled": (ctypes.c_int, [P, dp, dp, ip, ctypes.c_int64, dp]),
             "fo_threads": (ctypes.c_int, []),
         }
@@ -215,24 +217,49 @@ def moment(cfg: dict, f: np.ndarray) -> np.ndarray:
     return out
 
 
-def init(cfg: dict, C0: np.ndarray) -> np.ndarray:
-    """Initial populations f = f^eq(C0 with walls := c_wall): array (Q, *shape)."""
+def _field(cfg: dict, a, lead=()):
+    """A node field (or stack of fields) as contiguous FP64, or None."""
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(tuple(lead) + shape_of(cfg))
+    return a, _dp(a)
+
+
+def init(cfg: dict, C0: np.ndarray, Cw: np.ndarray | None = None) -> np.ndarray:
+    """Initial populations f = f^eq(C0 with walls := Dirichlet value): array (Q, *shape).
+
+    Cw (optional) is a node field of Dirichlet values (its wall entries are
+    used); without it every wall node takes cfg's c_wall.
+    """
     P = make_problem(cfg)
     C0 = np.ascontiguousarray(C0, dtype=np.float64).reshape(shape_of(cfg))
     f = np.zeros((Q_of(cfg),) + C0.shape)
-    _check(lib().fo_init(ctypes.byref(P), _dp(C0), _dp(f)), "init")
+    if Cw is None:
+        _check(lib().fo_init(ctypes.byref(P), _dp(C0), _dp(f)), "init")
+    else:
+        Cw, Cwp = _field(cfg, Cw)
+        _check(lib().fo_init_var(ctypes.byref(P), _dp(C0), Cwp, _dp(f)), "init_var")
     return f
 
 
-def step(cfg: dict, f: np.ndarray, nsteps: int, S: np.ndarray | None = None) -> np.ndarray:
-    """Advance populations by nsteps time steps; returns a new array."""
+def step(cfg: dict, f: np.ndarray, nsteps: int, S: np.ndarray | None = None, D: np.ndarray | None = None,
+         Cw: np.ndarray | None = None) -> np.ndarray:
+    """Advance populations by nsteps time steps; returns a new array.
+
+    Optional space-dependent coefficients (constant over the nsteps): S the
+    source field, D the diffusion tensor of every node, shape (d, d, *shape)
+    (MRT only), Cw the Dirichlet value of every node (wall entries used).
+    """
     P = make_problem(cfg)
+    d = int(cfg["dim"])
     f = np.array(f, dtype=np.float64, order="C", copy=True)
-    Sp = None
-    if S is not None:
-        S = np.ascontiguousarray(S, dtype=np.float64).reshape(shape_of(cfg))
-        Sp = _dp(S)
-    _check(lib().fo_step(ctypes.byref(P), _dp(f), Sp, int(nsteps)), "step")
+    S, Sp = _field(cfg, S)
+    if D is None and Cw is None:
+        _check(lib().fo_step(ctypes.byref(P), _dp(f), Sp, int(nsteps)), "step")
+        return f
+    D, Dp = _field(cfg, D, (d, d))
+    Cw, Cwp = _field(cfg, Cw)
+    _check(lib().fo_step_var(ctypes.byref(P), _dp(f), Sp, Dp, Cwp, int(nsteps)), "step_var")
     return f
 
 

@@ -454,8 +454,9 @@ int fo_equilibrium(const fo_problem* P, double C, const double* phi, double* feq
 }
 
 /* Collision with source at one node, equation (MRT-Coll) (or (LBE_FADE) for
- * BGK): f* = f - M^-1 Lambda M (f - f^eq) + w S dt. */
-static void collide(const fo_problem* P, const fo_lattice_t* L, const fo_collision* K,
+ * BGK): f* = f - M^-1 Lambda M (f - f^eq) + w S dt.  Lam is the relaxation
+ * matrix of this node (K->Lam unless the diffusion tensor varies in space). */
+static void collide(const fo_problem* P, const fo_lattice_t* L, const fo_collision* K, const double* Lam,
                     const double* f, const double* feq, double S, double* fstar)
 {
     const int Q = L->Q;
@@ -473,7 +474,7 @@ static void collide(const fo_problem* P, const fo_lattice_t* L, const fo_collisi
     }
     for (int r = 0; r < Q; ++r) {
         double s = 0.0;
-        for (int c = 0; c < Q; ++c) s += K->Lam[r * Q + c] * m[c];
+        for (int c = 0; c < Q; ++c) s += Lam[r * Q + c] * m[c];
         lm[r] = s;
     }
     for (int r = 0; r < Q; ++r) {
@@ -492,7 +493,7 @@ int fo_collide_node(const fo_problem* P, const double* f, double C, const double
     if (rc) return rc;
     lattice_of(P->dim, &L);
     equilibrium(P, &L, C, phi, feq);
-    collide(P, &L, &K, f, feq, S, fstar);
+    collide(P, &L, &K, K.Lam, f, feq, S, fstar);
     return FO_OK;
 }
 
@@ -525,9 +526,10 @@ static int on_wall(const fo_problem* P, const int64_t x[3])
  * outside the domain is unknown.  Then the Dirichlet rule, equation
  * (Dirichlet_BC) of Sec. 2.5: at a wall node with unknown set U,
  * f_b = (C_wall - sum_{i not in U} f_i) / |U| for b in U (|U| = 1 on faces;
- * the equal share at edges and corners is this implementation's reading). */
+ * the equal share at edges and corners is this implementation's reading).
+ * c_wall is the Dirichlet value of node y. */
 static void stream_node(const fo_problem* P, const fo_lattice_t* L, const double* fstar,
-                        int64_t nodes, int64_t y, double* fy /* Q */)
+                        int64_t nodes, int64_t y, double c_wall, double* fy /* Q */)
 {
     int64_t c[3];
     coords_of(P, y, c);
@@ -551,15 +553,17 @@ static void stream_node(const fo_problem* P, const fo_lattice_t* L, const double
         }
     }
     if (nu_known > 0) {
-        const double share = (P->c_wall - known) / (double)nu_known;
+        const double share = (c_wall - known) / (double)nu_known;
         for (int i = 0; i < L->Q; ++i)
             if (unknown[i]) fy[i] = share;
     }
 }
 
 /* Initial state (Algorithm 1, initialisations; reading: f(x, 0) is the
- * equilibrium of the initial concentration whose wall nodes carry C_wall). */
-int fo_init(const fo_problem* P, const double* C0, double* f)
+ * equilibrium of the initial concentration whose wall nodes carry the
+ * Dirichlet value).  Cw (nullable) gives a Dirichlet value per node (only its
+ * wall entries are read); NULL means P->c_wall on every wall node. */
+int fo_init_var(const fo_problem* P, const double* C0, const double* Cw, double* f)
 {
     fo_lattice_t L;
     int rc = validate(P);
@@ -576,7 +580,7 @@ int fo_init(const fo_problem* P, const double* C0, double* f)
     for (int64_t x = 0; x < nodes; ++x) {
         int64_t c[3];
         coords_of(P, x, c);
-        C[x] = on_wall(P, c) ? P->c_wall : C0[x];
+        C[x] = on_wall(P, c) ? (Cw ? Cw[x] : P->c_wall) : C0[x];
     }
     rc = fo_phi(P, C, Phi);
     if (!rc) {
@@ -593,13 +597,50 @@ int fo_init(const fo_problem* P, const double* C0, double* f)
     return rc;
 }
 
+int fo_init(const fo_problem* P, const double* C0, double* f) { return fo_init_var(P, C0, NULL, f); }
+
+/* Relaxation matrix of one node whose diffusion tensor is Dn (d x d,
+ * row-major): the paper lets D, hence lambda-bar and Lambda, depend on x
+ * (Sec. 2.3, and the exact-solution test of Sec. 3.4).  Lambda^{-1} is K's
+ * blockdiag(tau0, lambda-bar, tau_free) with the flux block replaced by
+ * lambda-bar(x) = Dn dt / (e^2 dx^2) + Id/2, inverted by Gauss-Jordan.
+ * Dn must be symmetric positive SEMI-definite (every principal minor >= 0):
+ * D(x) vanishes where x_mu = 0 in that test, and lambda-bar = Id/2 is still
+ * invertible there. */
+static int node_relaxation(const fo_problem* P, const fo_lattice_t* L, const fo_collision* K, const double* Dn,
+                           double* Lam /* Q x Q */)
+{
+    const int d = P->dim, Q = L->Q;
+    const double scale = P->dt / (L->e2 * P->dx * P->dx);
+    double Li[49];
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < a; ++b)
+            if (Dn[a * d + b] != Dn[b * d + a]) return FO_EINVAL;
+    for (int a = 0; a < d; ++a) {
+        if (!(Dn[a * d + a] >= 0.0)) return FO_EINVAL;
+        for (int b = a + 1; b < d; ++b)
+            if (!(Dn[a * d + a] * Dn[b * d + b] - Dn[a * d + b] * Dn[b * d + a] >= 0.0)) return FO_EINVAL;
+    }
+    if (d == 3) {
+        const double m3 = Dn[0] * (Dn[4] * Dn[8] - Dn[5] * Dn[7]) - Dn[1] * (Dn[3] * Dn[8] - Dn[5] * Dn[6]) +
+                          Dn[2] * (Dn[3] * Dn[7] - Dn[4] * Dn[6]);
+        if (!(m3 >= 0.0)) return FO_EINVAL;
+    }
+    memcpy(Li, K->Laminv, sizeof(double) * Q * Q);
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) Li[(1 + a) * Q + (1 + b)] = Dn[a * d + b] * scale + (a == b ? 0.5 : 0.0);
+    return invert(Q, Li, Lam);
+}
+
 /* Collision at every node: f -> f* (stages 1-2 of the time loop plus the
  * right-hand side of (MRT-Coll)).  C is the moment of f at the start of the
- * step. */
-static int collide_all(const fo_problem* P, const fo_lattice_t* L, const fo_collision* K,
+ * step.  LamN (nullable): relaxation matrix of every node, LamN[x*Q*Q + ...];
+ * NULL means K->Lam everywhere. */
+static int collide_all(const fo_problem* P, const fo_lattice_t* L, const fo_collision* K, const double* LamN,
                        const double* f, const double* S, double* fstar)
 {
     const int64_t nodes = nodes_of(P);
+    const int64_t QQ = (int64_t)L->Q * L->Q;
     double* C = (double*)malloc(sizeof(double) * nodes);
     double* Phi = (double*)malloc(sizeof(double) * nodes * P->dim);
     int rc = FO_ENOMEM;
@@ -613,7 +654,7 @@ static int collide_all(const fo_problem* P, const fo_lattice_t* L, const fo_coll
                 for (int i = 0; i < L->Q; ++i) fx[i] = f[(int64_t)i * nodes + x];
                 for (int mu = 0; mu < P->dim; ++mu) phi[mu] = Phi[(int64_t)mu * nodes + x];
                 equilibrium(P, L, C[x], phi, feq);
-                collide(P, L, K, fx, feq, S ? S[x] : 0.0, fs);
+                collide(P, L, K, LamN ? LamN + x * QQ : K->Lam, fx, feq, S ? S[x] : 0.0, fs);
                 for (int i = 0; i < L->Q; ++i) fstar[(int64_t)i * nodes + x] = fs[i];
             }
         }
@@ -623,31 +664,61 @@ static int collide_all(const fo_problem* P, const fo_lattice_t* L, const fo_coll
     return rc;
 }
 
-/* nsteps iterations of the time loop of Algorithm 1 on f in place.
- * S may be NULL (no source). */
-int fo_step(const fo_problem* P, double* f, const double* S, int64_t nsteps)
+/* nsteps iterations of the time loop of Algorithm 1 on f in place, with
+ * optional space-dependent coefficients:
+ *   S     (nullable) source field, constant over the nsteps;
+ *   Dfld  (nullable) diffusion tensor of every node, Dfld[(a*d + b)*nodes + x]
+ *         (MRT only: BGK has one relaxation time for every moment);
+ *   Cw    (nullable) Dirichlet value of every node (wall entries are read).
+ * NULL takes the constant P->D / P->c_wall.  A time-dependent source or wall
+ * value is applied by calling this once per step with the fields of that
+ * step. */
+int fo_step_var(const fo_problem* P, double* f, const double* S, const double* Dfld, const double* Cw,
+                int64_t nsteps)
 {
     fo_lattice_t L;
     fo_collision K;
     int rc = make_collision(P, &K);
     if (rc) return rc;
     if (nsteps < 0) return FO_EINVAL;
+    if (Dfld && P->collision != 1) return FO_EINVAL;
     lattice_of(P->dim, &L);
     const int64_t nodes = nodes_of(P);
+    const int d = P->dim;
+    const int64_t QQ = (int64_t)L.Q * L.Q;
     double* fstar = (double*)malloc(sizeof(double) * nodes * L.Q);
-    if (!fstar) return FO_ENOMEM;
+    double* LamN = Dfld ? (double*)malloc(sizeof(double) * nodes * QQ) : NULL;
+    if (!fstar || (Dfld && !LamN)) {
+        free(fstar);
+        free(LamN);
+        return FO_ENOMEM;
+    }
+    if (Dfld) {
+        for (int64_t x = 0; x < nodes && !rc; ++x) {
+            double Dn[9];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) Dn[a * d + b] = Dfld[(int64_t)(a * d + b) * nodes + x];
+            rc = node_relaxation(P, &L, &K, Dn, LamN + x * QQ);
+        }
+    }
     for (int64_t m = 0; m < nsteps && !rc; ++m) {
-        rc = collide_all(P, &L, &K, f, S, fstar);
+        rc = collide_all(P, &L, &K, LamN, f, S, fstar);
         if (rc) break;
 #pragma omp parallel for schedule(static)
         for (int64_t y = 0; y < nodes; ++y) {
             double fy[7];
-            stream_node(P, &L, fstar, nodes, y, fy);
+            stream_node(P, &L, fstar, nodes, y, Cw ? Cw[y] : P->c_wall, fy);
             for (int i = 0; i < L.Q; ++i) f[(int64_t)i * nodes + y] = fy[i];
         }
     }
     free(fstar);
+    free(LamN);
     return rc;
+}
+
+int fo_step(const fo_problem* P, double* f, const double* S, int64_t nsteps)
+{
+    return fo_step_var(P, f, S, NULL, NULL, nsteps);
 }
 
 /* One iteration of the time loop evaluated only at the listed nodes: given
@@ -717,7 +788,7 @@ int fo_step_sampled(const fo_problem* P, const double* f, const double* S,
                 for (int j = 0; j < Q; ++j) fs[j] = f[(int64_t)j * nodes + s];
                 for (int mu = 0; mu < P->dim; ++mu) ph[mu] = phi[(int64_t)mu * count * Q + k * Q + i];
                 equilibrium(P, &L, C[s], ph, feq);
-                collide(P, &L, &K, fs, feq, S ? S[s] : 0.0, fst);
+                collide(P, &L, &K, K.Lam, fs, feq, S ? S[s] : 0.0, fst);
                 fy[i] = fst[i];
                 known += fy[i];
             }

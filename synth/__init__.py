@@ -146,3 +146,57 @@ def small(dim: int, n, *, seed: int = 0, collision: str = "MRT", alpha=None, p=N
         cfg["source"] = dict(kind="random", seed=seed + 2000, scale=1e-3)
     cfg.update(kw)
     return cfg
+
+
+# ---------------------------------------------------------------------------
+# Power-law problems with an exact solution (Sec. 3.4, equations (Def_D_AS)
+# and (exsolFADE_3D)): on [0, L]^d with p = 1, u = 0, g = 1,
+#   D_mumu(x) = x_mu^alpha_mu Gamma(a_mu + 2 - alpha_mu) / Gamma(a_mu + 2),
+#   S(x, t)   = -(d + 1) e^-t prod_mu x_mu^a_mu,
+#   C(x, t)   = e^-t prod_mu x_mu^a_mu  (also the initial and wall values).
+# With eps != 0 (2D only) the tensor also gets the off-diagonal entry
+# D_01 = D_10 = eps x_0 x_1, and the source gains the divergence of the extra
+# flux, S -= e^-t eps [G_1 (a_0 + 1) x_0^a_0 x_1^(a_1 + 2 - alpha_1)
+#                      + G_0 (a_1 + 1) x_1^a_1 x_0^(a_0 + 2 - alpha_0)],
+# G_mu = Gamma(a_mu + 1) / Gamma(a_mu + 2 - alpha_mu), because the left
+# Riemann-Liouville derivative of order alpha - 1 of x^a is
+# G x^(a + 1 - alpha).  These fields are problem data, not the method.
+
+class PowerLawProblem:
+    """Fields of the exact-solution workload on an n^d grid (walls included)."""
+
+    def __init__(self, dim: int, n: int, dt: float, *, alpha=None, a=None, eps: float = 0.0, length: float = 1.0,
+                 D_const: float = 0.5, tau_free: float = 1.0):
+        if eps != 0.0 and dim != 2:
+            raise ValueError("the off-diagonal variant is 2D")
+        self.dim = d = dim
+        self.alpha = list(alpha) if alpha is not None else ([1.5, 1.7] if d == 2 else [1.5, 1.7, 1.9])
+        self.a = list(a) if a is not None else ([0.4, 0.7] if d == 2 else [2.0, 2.0, 2.0])
+        self.eps = float(eps)
+        dx = length / (n - 1)
+        self.cfg = dict(dim=d, n=[n] * d, dx=dx, dt=float(dt), collision="MRT", alpha=self.alpha, p=[1.0] * d,
+                        g=[1.0] * d, u=[0.0] * d, D=(D_const * np.eye(d)).tolist(), tau_free=[tau_free] * 4,
+                        tau0=1.0, c_wall=0.0, steps=0, name=f"powerlaw_{d}d_{n}")
+        x = np.arange(n, dtype=np.float64) * dx
+        grids = np.meshgrid(*([x] * d), indexing="ij")  # slowest first
+        X = list(reversed(grids))                        # X[mu]: coordinate along axis mu
+        al, aa = self.alpha, self.a
+        self.base = np.ones(X[0].shape)
+        for mu in range(d):
+            self.base = self.base * X[mu] ** aa[mu]
+        self.D = np.zeros((d, d) + self.base.shape)
+        for mu in range(d):
+            self.D[mu, mu] = X[mu] ** al[mu] * math.gamma(aa[mu] + 2 - al[mu]) / math.gamma(aa[mu] + 2)
+        self.extra = np.zeros(self.base.shape)
+        if self.eps != 0.0:
+            self.D[0, 1] = self.D[1, 0] = self.eps * X[0] * X[1]
+            G0 = math.gamma(aa[0] + 1) / math.gamma(aa[0] + 2 - al[0])
+            G1 = math.gamma(aa[1] + 1) / math.gamma(aa[1] + 2 - al[1])
+            self.extra = self.eps * (G1 * (aa[0] + 1) * X[0] ** aa[0] * X[1] ** (aa[1] + 2 - al[1])
+                                     + G0 * (aa[1] + 1) * X[1] ** aa[1] * X[0] ** (aa[0] + 2 - al[0]))
+
+    def exact(self, t: float) -> np.ndarray:
+        return math.exp(-t) * self.base
+
+    def source(self, t: float) -> np.ndarray:
+        return -math.exp(-t) * ((self.dim + 1) * self.base + self.extra)
