@@ -108,13 +108,41 @@ LBM_API int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_par
 LBM_API void lbm_fade_destroy(lbm_fade_t h);
 
 /* Set the initial concentration (host or device, nodes floats).  Wall nodes are
- * overwritten with c_wall, Phi(C0) is computed, and f := f^eq(C0, Phi(C0))
+ * overwritten with c_wall (or the values of lbm_fade_set_wall), Phi(C0) is computed, and f := f^eq(C0, Phi(C0))
  * (reading of Algorithm 1's initialisations: the paper does not fix f(x, 0)). */
 LBM_API int lbm_fade_set_C(lbm_fade_t h, const float* C0, int32_t on_device, void* stream);
 
-/* Set a constant-in-time source field S (host or device, nodes floats), added as
- * w_i S dt after collision (equation (LBE_FADE)); NULL removes the source. */
+/* Set the source field S (host or device, nodes floats), added as w_i S dt
+ * after collision (equation (LBE_FADE)) by every later step until the next
+ * call (a time-dependent source is set before every step); NULL removes it. */
 LBM_API int lbm_fade_set_source(lbm_fade_t h, const float* S, int32_t on_device, void* stream);
+
+/* Space-dependent diffusion tensor D(x) (Sec. 2.3: lambda-bar and Lambda may
+ * depend on x; the exact-solution test of Sec. 3.4 uses D_mumu(x) proportional
+ * to x_mu^alpha_mu).  D is host or device, d*d node fields, field-major:
+ * D[(a*d + b)*nodes + node], FP32, each node's tensor symmetric and positive
+ * SEMI-definite (it may vanish, e.g. on the x_mu = 0 walls).  Computes on the
+ * host in FP64, once per call, lambda-bar(x) = D(x) dt/(e^2 dx^2) + Id/2 and
+ * stores the difference lambda-bar(x)^-1 - lambda-bar^-1 from the flux block
+ * of the handle's constant tensor (d(d+1)/2 FP32 fields on the device), which
+ * the collision adds to its flux block at every node; the constant D of
+ * create stays the reference (any SPD choice).  NULL goes back to the constant
+ * D.  MRT only (LBM_EINVAL for BGK, whose single relaxation time covers every
+ * moment).  Errors: LBM_EINVAL naming the first node whose tensor is not
+ * finite, symmetric (relative 1e-6) or positive semi-definite (principal
+ * minors >= -1e-6 times the product of their diagonal entries); the handle is
+ * then unchanged.  Synchronises `stream` (device input is staged through the
+ * host).  Adds 4 d(d+1)/2 bytes per node to the collide kernel's traffic.  The
+ * adjoint refuses a handle with a space-dependent D or wall values. */
+LBM_API int lbm_fade_set_diffusion(lbm_fade_t h, const float* D, int32_t on_device, void* stream);
+
+/* Non-homogeneous Dirichlet values (Sec. 2.5 with a value per wall node):
+ * Cw is host or device, one node field; the Dirichlet rule of every later
+ * step, and the wall overwrite of set_C, use Cw[node] at wall nodes (interior
+ * entries are ignored) instead of c_wall.  Time-dependent walls (Sec. 3.4) are
+ * set before every step; the value written by a step is read when that step
+ * runs.  NULL goes back to c_wall.  Host input synchronises `stream`. */
+LBM_API int lbm_fade_set_wall(lbm_fade_t h, const float* Cw, int32_t on_device, void* stream);
 
 /* Advance n >= 0 time steps.  Asynchronous; the launches of one step are: the
  * fractional-term GEMM of every axis, then the fused collide-stream-boundary-

@@ -16,7 +16,8 @@ ERROR_NAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM", LBM_EDEVICE: 
                LBM_ENONFINITE: "LBM_ENONFINITE", LBM_ESTATE: "LBM_ESTATE"}
 
 # Every symbol include/lbm_fade.h declares.
-EXPORTED = ["lbm_fade_create", "lbm_fade_destroy", "lbm_fade_set_C", "lbm_fade_set_source", "lbm_fade_step",
+EXPORTED = ["lbm_fade_create", "lbm_fade_destroy", "lbm_fade_set_C", "lbm_fade_set_source", "lbm_fade_set_diffusion",
+            "lbm_fade_set_wall", "lbm_fade_step",
             "lbm_fade_get_C", "lbm_fade_get_f", "lbm_fade_set_f", "lbm_fade_apply_phi", "lbm_fade_adjoint",
             "lbm_fade_last_error", "lbm_fade_version"]
 
@@ -72,6 +73,8 @@ def lib() -> ctypes.CDLL:
         "lbm_fade_destroy": (None, [H]),
         "lbm_fade_set_C": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),
         "lbm_fade_set_source": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),
+        "lbm_fade_set_diffusion": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),
+        "lbm_fade_set_wall": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),
         "lbm_fade_step": (ctypes.c_int, [H, ctypes.c_int64, vp]),
         "lbm_fade_get_C": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),
         "lbm_fade_get_f": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),

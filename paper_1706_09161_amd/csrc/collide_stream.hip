@@ -36,6 +36,8 @@
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -71,9 +73,33 @@ __device__ __forceinline__ uint32_t pack_hilo(float c)
     return hi | (lo << 16);
 }
 
+// Index of entry (a, b), a <= b, of a symmetric d x d block stored as its
+// upper triangle row by row: (00, 01, 11) in 2D, (00, 01, 02, 11, 12, 22) in 3D.
+__host__ __device__ constexpr int sym_index(int d, int a, int b) { return a * d - a * (a - 1) / 2 + (b - a); }
+
+// Space-dependent diffusion tensor (Sec. 2.3: lambda-bar and Lambda may vary
+// with x): the node's flux block of Lambda is the constant block plus dB (the
+// symmetric difference lambda-bar(x)^-1 - lambda-bar^-1).  The flux moments
+// are m_{1+b} = dev_{2b+1} - dev_{2b+2}, and column 1+a of M^-1 holds +1/2 at
+// population 2a+1 and -1/2 at 2a+2, so the extra relaxation
+// M^-1 (0, dB m_flux, 0) moves -delta_a/2 into f*_{2a+1} and +delta_a/2 into
+// f*_{2a+2}, delta_a = sum_b dB_ab m_{1+b}.
 template <int Q>
+__device__ __forceinline__ float flux_delta(const float (&dev)[Q], const float* db, int a)
+{
+    constexpr int d = (Q - 1) / 2;
+    float s = 0.f;
+#pragma unroll
+    for (int b = 0; b < d; ++b) {
+        const float m = dev[2 * b + 1] - dev[2 * b + 2];
+        s = fmaf(db[a <= b ? sym_index(d, a, b) : sym_index(d, b, a)], m, s);
+    }
+    return s;
+}
+
+template <int Q, bool VAR>
 __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
-                                    float S, float (&fs)[Q])
+                                    float S, const float* db, float (&fs)[Q])
 {
     constexpr int d = (Q - 1) / 2;
     float C = 0.f;
@@ -102,12 +128,21 @@ __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q]
         fs[i] = f[i] - r;
         fs[i] = fmaf(cc.wSdt[i], S, fs[i]);
     }
+    if (VAR) {
+#pragma unroll
+        for (int a = 0; a < d; ++a) {
+            const float h = 0.5f * flux_delta<Q>(dev, db, a);
+            fs[2 * a + 1] -= h;
+            fs[2 * a + 2] += h;
+        }
+    }
 }
 
-// Post-collision populations a and b of one node (a halo node at a strip edge).
-template <int Q>
-__device__ inline void collide_two(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
-                                   float S, int a, int b, float& fa, float& fb)
+// Post-collision populations 1 and 2 (the two that cross x) of one node (a
+// halo node at a strip edge).  With VAR, db holds row 0 of the node's dB.
+template <int Q, bool VAR>
+__device__ inline void collide_x_pair(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
+                                      float S, const float* db, float& f1, float& f2)
 {
     constexpr int d = (Q - 1) / 2;
     float C = 0.f;
@@ -125,21 +160,31 @@ __device__ inline void collide_two(const CollideConsts& cc, const float (&f)[Q],
         feq[2 * mu + 1] = x + y;
         feq[2 * mu + 2] = x - y;
     }
+    float dev[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) dev[j] = f[j] - feq[j];
     float ra = 0.f, rb = 0.f;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-        const float dev = f[j] - feq[j];
-        ra = fmaf(cc.R[a * Q + j], dev, ra);
-        rb = fmaf(cc.R[b * Q + j], dev, rb);
+        ra = fmaf(cc.R[1 * Q + j], dev[j], ra);
+        rb = fmaf(cc.R[2 * Q + j], dev[j], rb);
     }
-    fa = fmaf(cc.wSdt[a], S, f[a] - ra);
-    fb = fmaf(cc.wSdt[b], S, f[b] - rb);
+    f1 = fmaf(cc.wSdt[1], S, f[1] - ra);
+    f2 = fmaf(cc.wSdt[2], S, f[2] - rb);
+    if (VAR) {
+        // row 0 of dB: db[b] = dB_0b
+        float s = 0.f;
+#pragma unroll
+        for (int b = 0; b < d; ++b) s = fmaf(db[b], dev[2 * b + 1] - dev[2 * b + 2], s);
+        f1 -= 0.5f * s;
+        f2 += 0.5f * s;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // 2D D2Q5 fused kernel.  Rows move through a ring of D slots: while row y + 1
 // is collided, the loads of rows y + 2 .. y + D are in flight.
-template <bool HAS_S, bool PACK, typename OFF>
+template <bool HAS_S, bool PACK, bool VAR, typename OFF>
 __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
                                                          float* __restrict__ fout, const float* __restrict__ Phi,
                                                          const float* __restrict__ S, float* __restrict__ Cout,
@@ -164,10 +209,14 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
 #pragma unroll
     for (int i = 0; i < 5; ++i) fi[i] = fin + i * nodes;
     const float* ph1 = Phi + nodes;
+    const float* dbk[3];  // VAR: the three fields of dB (00, 01, 11)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dbk[k] = VAR ? cc.dB + k * nodes : nullptr;
 
     struct Row {
         float f[5], phi[2], s;  // this lane's node
         float h[5], hphi[2], hs;  // the node just outside the strip (left half: x0 - 1, right half: x0 + 64)
+        float db[3], hdb[2];      // VAR: dB of the node, row 0 of dB of the halo node
     };
     // Nodes outside the box read the nearest node inside it: every population
     // they send into the box arrives through a wall and is replaced by the
@@ -188,13 +237,19 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
         r.hphi[0] = ldf(Phi, bh);
         r.hphi[1] = ldf(ph1, bh);
         r.hs = HAS_S ? ldf(S, bh) : 0.f;
+        if (VAR) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r.db[k] = ldf(dbk[k], b);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) r.hdb[k] = ldf(dbk[k], bh);
+        }
     };
     // collision of a row: this lane's node, and the population its halo node
     // sends into the strip (f*_1 from the left neighbour, f*_2 from the right)
     auto collide_row = [&](const Row& r, float (&fs)[5], float& hv) {
-        collide_node<5>(cc, r.f, r.phi, r.s, fs);
+        collide_node<5, VAR>(cc, r.f, r.phi, r.s, r.db, fs);
         float h1, h2;
-        collide_two<5>(cc, r.h, r.hphi, r.hs, 1, 2, h1, h2);
+        collide_x_pair<5, VAR>(cc, r.h, r.hphi, r.hs, r.hdb, h1, h2);
         hv = lane < 32 ? h1 : h2;
     };
 
@@ -233,7 +288,11 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
                 else known += f[i];
             }
             if (nu > 0) {
-                const float share = (cc.c_wall - known) * inv_count(nu);
+                // Dirichlet value of this wall node (clamped address: lanes past
+                // the grid and rows past the chunk are never stored)
+                const float cw =
+                    VAR ? ldf(cc.Cw, (OFF)(((int64_t)min(y, ny - 1) * nx + xc) * 4)) : cc.c_wall;
+                const float share = (cw - known) * inv_count(nu);
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
                     if (unk[i]) f[i] = share;
@@ -263,7 +322,7 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
 // planes (the loads of planes z + 2 .. z + D are in flight while plane z + 1
 // is collided).  f*_3 / f*_4 cross rows through LDS, double-buffered by plane
 // parity so one barrier per plane suffices.
-template <int NY, bool HAS_S, bool PACK, typename OFF>
+template <int NY, bool HAS_S, bool PACK, bool VAR, typename OFF>
 __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, const float* __restrict__ fin,
                                                              float* __restrict__ fout, const float* __restrict__ Phi,
                                                              const float* __restrict__ S, float* __restrict__ Cout,
@@ -298,6 +357,7 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
     struct Plane {
         float f[7], phi[3], s;
         float h[7], hphi[3], hs;  // the node just outside the strip (left half: x0 - 1, right half: x0 + 64)
+        float db[6], hdb[3];      // VAR: dB of the node, row 0 of dB of the halo node
     };
     // nodes outside the box read the nearest node inside it (see the 2D kernel)
     const int64_t yoff = (int64_t)min(max(y, 0), ny - 1) * nx;
@@ -316,11 +376,17 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu) p.hphi[mu] = ldf(Phi, bh + mu * fb);
         p.hs = HAS_S ? ldf(S, bh) : 0.f;
+        if (VAR) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) p.db[k] = ldf(cc.dB, bm + k * fb);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) p.hdb[k] = ldf(cc.dB, bh + k * fb);
+        }
     };
     auto collide_at = [&](const Plane& p, float (&fs)[7], float& hv) {
-        collide_node<7>(cc, p.f, p.phi, p.s, fs);
+        collide_node<7, VAR>(cc, p.f, p.phi, p.s, p.db, fs);
         float h1, h2;
-        collide_two<7>(cc, p.h, p.hphi, p.hs, 1, 2, h1, h2);
+        collide_x_pair<7, VAR>(cc, p.h, p.hphi, p.hs, p.hdb, h1, h2);
         hv = lane < 32 ? h1 : h2;
     };
 
@@ -363,7 +429,9 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
                 else known += f[i];
             }
             if (nu > 0) {
-                const float share = (cc.c_wall - known) * inv_count(nu);
+                const float cw =
+                    VAR ? ldf(cc.Cw, (OFF)(((int64_t)min(z, nz - 1) * plane + xyc) * 4)) : cc.c_wall;
+                const float share = (cw - known) * inv_count(nu);
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
                     if (unk[i]) f[i] = share;
@@ -425,7 +493,13 @@ __global__ void wall_overwrite(CollideConsts cc, float* __restrict__ C, int64_t 
         r /= cc.n[mu];
         wall = wall || c == 0 || c == cc.n[mu] - 1;
     }
-    if (wall) C[i] = cc.c_wall;
+    if (wall) C[i] = cc.Cw ? cc.Cw[i] : cc.c_wall;
+}
+
+__global__ void fill_kernel(float* __restrict__ p, int64_t count, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
 }
 
 template <int Q>
@@ -462,6 +536,32 @@ int64_t nodes_of(const CollideConsts& cc)
 
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Calls f(integral_constant<bool, a>, ..., ...) for the run-time flags a, b, c:
+// picks one of the eight instantiations of a kernel template.
+template <typename F>
+void with_flags(bool a, bool b, bool c, F&& f)
+{
+    using T = std::true_type;
+    using N = std::false_type;
+    if (a) {
+        if (b) {
+            if (c) f(T{}, T{}, T{});
+            else f(T{}, T{}, N{});
+        } else {
+            if (c) f(T{}, N{}, T{});
+            else f(T{}, N{}, N{});
+        }
+    } else {
+        if (b) {
+            if (c) f(N{}, T{}, T{});
+            else f(N{}, T{}, N{});
+        } else {
+            if (c) f(N{}, N{}, T{});
+            else f(N{}, N{}, N{});
+        }
+    }
+}
+
 // Rows per wavefront of the 2D kernel forced by LBM_COLLIDE_ROWS (tuning; 0 = automatic).
 int collide_rows_override()
 {
@@ -477,6 +577,9 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
 {
     // 32-bit byte offsets while every array (at most 7 fields of the node count) fits in 4 GiB
     const bool small = nodes_of(cc) * 7 * 4 < ((int64_t)1 << 32);
+    // space-dependent diffusion tensor and wall values (both fields present)
+    const bool var = cc.dB != nullptr;
+    if (var && !cc.Cw) return hipErrorInvalidValue;
     if (cc.dim == 2) {
         const int nx = cc.n[0], ny = cc.n[1];
         const int strips = (nx + kStrip - 1) / kStrip;
@@ -492,56 +595,42 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out, rows,
                                strips, waves);
         };
-        if (small) {
-            if (S) {
-                if (Cp_out) go(collide_stream_2d<true, true, uint32_t>);
-                else go(collide_stream_2d<true, false, uint32_t>);
-            } else {
-                if (Cp_out) go(collide_stream_2d<false, true, uint32_t>);
-                else go(collide_stream_2d<false, false, uint32_t>);
-            }
-        } else {
-            if (S) {
-                if (Cp_out) go(collide_stream_2d<true, true, uint64_t>);
-                else go(collide_stream_2d<true, false, uint64_t>);
-            } else {
-                if (Cp_out) go(collide_stream_2d<false, true, uint64_t>);
-                else go(collide_stream_2d<false, false, uint64_t>);
-            }
-        }
+        with_flags(S != nullptr, Cp_out != nullptr, var, [&](auto hs, auto pk, auto vr) {
+            if (small)
+                go(collide_stream_2d<decltype(hs)::value, decltype(pk)::value, decltype(vr)::value, uint32_t>);
+            else
+                go(collide_stream_2d<decltype(hs)::value, decltype(pk)::value, decltype(vr)::value, uint64_t>);
+        });
         return hipGetLastError();
     }
-    constexpr int NY = 16;
-    const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
-    const int sx = (nx + kStrip - 1) / kStrip;
-    const int sy = (ny + (NY - 2) - 1) / (NY - 2);
-    // long z marches amortise the two halo planes; at least 2 workgroups per CU
-    int planes = 64;
-    while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 512) planes /= 2;
-    const int chunks = (nz + planes - 1) / planes;
-    const int64_t blocks = (int64_t)sx * sy * chunks;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    auto go = [&](auto kern) {
+    // NY rows per workgroup: 16 (one wave per row, 4 waves per SIMD, at most
+    // 128 VGPRs); the space-dependent variant holds 9 more values per ring
+    // plane and runs 8 rows (256 VGPRs) rather than spill.
+    auto launch3d = [&](auto ny_c, auto hs, auto pk, auto vr) {
+        constexpr int NY = decltype(ny_c)::value;
+        const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
+        const int sx = (nx + kStrip - 1) / kStrip;
+        const int sy = (ny + (NY - 2) - 1) / (NY - 2);
+        // long z marches amortise the two halo planes; at least 2 workgroups per CU
+        int planes = 64;
+        while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 512) planes /= 2;
+        const int chunks = (nz + planes - 1) / planes;
+        const int64_t blocks = (int64_t)sx * sy * chunks;
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        constexpr bool HS = decltype(hs)::value, PK = decltype(pk)::value, VR = decltype(vr)::value;
+        auto kern = small ? collide_stream_3d<NY, HS, PK, VR, uint32_t> : collide_stream_3d<NY, HS, PK, VR, uint64_t>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out,
                            planes, sx, sy);
+        return hipSuccess;
     };
-    if (small) {
-        if (S) {
-            if (Cp_out) go(collide_stream_3d<NY, true, true, uint32_t>);
-            else go(collide_stream_3d<NY, true, false, uint32_t>);
-        } else {
-            if (Cp_out) go(collide_stream_3d<NY, false, true, uint32_t>);
-            else go(collide_stream_3d<NY, false, false, uint32_t>);
-        }
-    } else {
-        if (S) {
-            if (Cp_out) go(collide_stream_3d<NY, true, true, uint64_t>);
-            else go(collide_stream_3d<NY, true, false, uint64_t>);
-        } else {
-            if (Cp_out) go(collide_stream_3d<NY, false, true, uint64_t>);
-            else go(collide_stream_3d<NY, false, false, uint64_t>);
-        }
-    }
+    hipError_t e = hipSuccess;
+    with_flags(S != nullptr, Cp_out != nullptr, var, [&](auto hs, auto pk, auto vr) {
+        if constexpr (decltype(vr)::value)
+            e = launch3d(std::integral_constant<int, 8>{}, hs, pk, vr);
+        else
+            e = launch3d(std::integral_constant<int, 16>{}, hs, pk, vr);
+    });
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -565,6 +654,12 @@ hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t 
 {
     const int64_t nodes = nodes_of(cc);
     hipLaunchKernelGGL(wall_overwrite, dim3(blocks_for(nodes, 256)), dim3(256), 0, s, cc, C, nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, int64_t count, float v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count, v);
     return hipGetLastError();
 }
 

@@ -390,6 +390,7 @@ int build_step_graph(lbm_fade* h)
     h->graph = g;
     h->gcur = cur0;
     h->gS = h->S;
+    h->gdB = h->cc.dB;
     graph_key(h->gkey);
     return LBM_OK;
 }
@@ -399,6 +400,95 @@ int refresh_C(lbm_fade* h, hipStream_t s)
 {
     HIP_TRY(lbm::launch_moment(h->cc, h->f[h->cur], h->C, s));
     if (h->Cp) HIP_TRY(lbm::launch_pack_bf16(h->C, h->Cp, h->nodes, s));
+    return LBM_OK;
+}
+
+// The two fields of the space-dependent path, allocated together on first
+// use with neutral contents (dB = 0, Cw = c_wall).
+int ensure_var_fields(lbm_fade* h, hipStream_t s)
+{
+    if (h->dB) return LBM_OK;
+    const int ncomp = h->dim * (h->dim + 1) / 2;
+    float *dB = nullptr, *Cw = nullptr;
+    if (hipMalloc(&dB, sizeof(float) * ncomp * h->nodes) != hipSuccess ||
+        hipMalloc(&Cw, sizeof(float) * h->nodes) != hipSuccess) {
+        (void)hipFree(dB);
+        return fail(LBM_ENOMEM, "hipMalloc of the space-dependent fields failed");
+    }
+    h->dB = dB;
+    h->Cw = Cw;
+    HIP_TRY(lbm::launch_fill(dB, ncomp * h->nodes, 0.f, s));
+    HIP_TRY(lbm::launch_fill(Cw, h->nodes, h->cc.c_wall, s));
+    h->cc.dB = dB;
+    h->cc.Cw = Cw;
+    return LBM_OK;
+}
+
+// Frees the fields once neither is in use (the kernels go back to the
+// constant path).
+int release_var_fields(lbm_fade* h, hipStream_t s)
+{
+    if (h->var_D || h->var_wall || !h->dB) return LBM_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(h->dB);
+    (void)hipFree(h->Cw);
+    h->dB = h->Cw = nullptr;
+    h->cc.dB = h->cc.Cw = nullptr;
+    return LBM_OK;
+}
+
+// dB of every node from a field of d x d tensors, FP64 on the host:
+// lambda-bar(x) = D(x) dt / (e^2 dx^2) + Id/2 (equation (D_ab) at each node),
+// dB(x) = lambda-bar(x)^-1 - lambda-bar^-1.  D(x) must be finite, symmetric
+// and positive semi-definite (every principal minor >= 0 up to FP32
+// rounding); the node of the first violation is reported.
+int diffusion_blocks(lbm_fade* h, const float* D, std::vector<float>& out)
+{
+    const int d = h->dim, ncomp = d * (d + 1) / 2;
+    const int64_t nodes = h->nodes;
+    const double scale = h->grid.dt / (h->e2 * h->grid.dx * h->grid.dx);
+    out.assign((size_t)ncomp * nodes, 0.f);
+    auto bad = [&](int64_t x, const char* why) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "D(x) at node %lld is %s", (long long)x, why);
+        return fail(LBM_EINVAL, msg);
+    };
+    for (int64_t x = 0; x < nodes; ++x) {
+        double Dn[9], lam[9], inv[9];
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                Dn[a * d + b] = (double)D[(int64_t)(a * d + b) * nodes + x];
+                if (!isfinite(Dn[a * d + b])) return bad(x, "not finite");
+            }
+        for (int a = 0; a < d; ++a)
+            for (int b = a + 1; b < d; ++b) {
+                const double u = Dn[a * d + b], v = Dn[b * d + a];
+                if (fabs(u - v) > 1e-6 * (fabs(u) + fabs(v))) return bad(x, "not symmetric");
+                Dn[a * d + b] = Dn[b * d + a] = 0.5 * (u + v);
+            }
+        // principal minors
+        const double tol = 1e-6;
+        for (int a = 0; a < d; ++a)
+            if (!(Dn[a * d + a] >= 0.0)) return bad(x, "not positive semi-definite");
+        for (int a = 0; a < d; ++a)
+            for (int b = a + 1; b < d; ++b) {
+                const double p = Dn[a * d + a] * Dn[b * d + b];
+                if (!(p - Dn[a * d + b] * Dn[a * d + b] >= -tol * p)) return bad(x, "not positive semi-definite");
+            }
+        if (d == 3) {
+            const double det = Dn[0] * (Dn[4] * Dn[8] - Dn[5] * Dn[7]) - Dn[1] * (Dn[3] * Dn[8] - Dn[5] * Dn[6]) +
+                               Dn[2] * (Dn[3] * Dn[7] - Dn[4] * Dn[6]);
+            if (!(det >= -tol * Dn[0] * Dn[4] * Dn[8])) return bad(x, "not positive semi-definite");
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) lam[a * d + b] = Dn[a * d + b] * scale + (a == b ? 0.5 : 0.0);
+        if (!small_inverse(d, lam, inv)) return bad(x, "singular");
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b) {
+                const int k = a * d - a * (a - 1) / 2 + (b - a);
+                out[(size_t)k * nodes + x] = (float)(inv[a * d + b] - h->lam_inv[a * d + b]);
+            }
+    }
     return LBM_OK;
 }
 
@@ -596,6 +686,8 @@ void lbm_fade_destroy(lbm_fade_t h)
     (void)hipFree(h->C);
     (void)hipFree(h->Phi);
     (void)hipFree(h->S);
+    (void)hipFree(h->dB);
+    (void)hipFree(h->Cw);
     (void)hipFree(h->Cp);
     (void)hipFree(h->Cp_tmp);
     (void)hipFree(h->opmem);
@@ -646,6 +738,62 @@ int lbm_fade_set_source(lbm_fade_t h, const float* S, int32_t on_device, void* s
     return LBM_OK;
 }
 
+int lbm_fade_set_diffusion(lbm_fade_t h, const float* D, int32_t on_device, void* stream)
+{
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    if (h->params.collision != LBM_MRT)
+        return fail(LBM_EINVAL, "a space-dependent D needs the MRT collision (BGK relaxes every moment alike)");
+    int rc = check_device(h);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    const int d = h->dim, ncomp = d * (d + 1) / 2;
+    if (!D) {
+        if (h->var_D) {
+            h->var_D = false;
+            HIP_TRY(lbm::launch_fill(h->dB, ncomp * h->nodes, 0.f, s));
+        }
+        return release_var_fields(h, s);
+    }
+    std::vector<float> staged;
+    const float* src = D;
+    if (on_device) {
+        staged.resize((size_t)d * d * h->nodes);
+        HIP_TRY(hipMemcpyAsync(staged.data(), D, sizeof(float) * staged.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        src = staged.data();
+    }
+    std::vector<float> blocks;
+    rc = diffusion_blocks(h, src, blocks);
+    if (rc) return rc;
+    rc = ensure_var_fields(h, s);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(h->dB, blocks.data(), sizeof(float) * blocks.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // blocks is freed on return
+    h->var_D = true;
+    return LBM_OK;
+}
+
+int lbm_fade_set_wall(lbm_fade_t h, const float* Cw, int32_t on_device, void* stream)
+{
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    int rc = check_device(h);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    if (!Cw) {
+        if (h->var_wall) {
+            h->var_wall = false;
+            HIP_TRY(lbm::launch_fill(h->Cw, h->nodes, h->cc.c_wall, s));
+        }
+        return release_var_fields(h, s);
+    }
+    rc = ensure_var_fields(h, s);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(h->Cw, Cw, sizeof(float) * h->nodes, kind_to_dev(on_device), s));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(s));
+    h->var_wall = true;
+    return LBM_OK;
+}
+
 int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream)
 {
     if (!h) return fail(LBM_EINVAL, "null handle");
@@ -658,7 +806,8 @@ int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream)
     if (every == 0 && n >= kGraphSteps && graphs_enabled()) {
         int key[3];
         graph_key(key);
-        if (!h->gexec || h->gS != h->S || key[0] != h->gkey[0] || key[1] != h->gkey[1] || key[2] != h->gkey[2]) {
+        if (!h->gexec || h->gS != h->S || h->gdB != h->cc.dB || key[0] != h->gkey[0] || key[1] != h->gkey[1] ||
+            key[2] != h->gkey[2]) {
             rc = build_step_graph(h);
             if (rc) return rc;
         }
@@ -768,6 +917,8 @@ int lbm_fade_adjoint(lbm_fade_t h, int64_t n, int32_t ckpt_every, const float* g
     if (!h || !gC || !out) return fail(LBM_EINVAL, "null argument");
     if (n < 0 || ckpt_every <= 0) return fail(LBM_EINVAL, "need n >= 0 and ckpt_every > 0");
     if (!h->has_state) return fail(LBM_ESTATE, "set_C must be called before adjoint");
+    if (h->cc.dB)
+        return fail(LBM_EINVAL, "the adjoint takes constant D and wall values: reset set_diffusion / set_wall");
     int rc = check_device(h);
     if (rc) return rc;
     std::string msg;

@@ -24,6 +24,12 @@ struct lbm_fade {
     float* S = nullptr;
     uint32_t* Cp = nullptr;       // split-BF16 path: packed BF16 split of C, kept in sync with C
     uint32_t* Cp_tmp = nullptr;   // split-BF16 path: packed split of other inputs of the operator
+    // space-dependent coefficients (allocated together on first use; cc.dB / cc.Cw
+    // point at them while either is in use)
+    float* dB = nullptr;          // d(d+1)/2 fields: lambda-bar(x)^-1 - lambda-bar^-1 (upper triangle)
+    float* Cw = nullptr;          // Dirichlet value of every node
+    bool var_D = false;           // dB set by lbm_fade_set_diffusion (else zero)
+    bool var_wall = false;        // Cw set by lbm_fade_set_wall (else c_wall)
     void* opmem = nullptr;  // generators, corrections and BF16 splits of all axes
     int* flag = nullptr;
     lbm::AxisOp ops[3];
@@ -43,6 +49,7 @@ struct lbm_fade {
     hipGraphExec_t gexec = nullptr;
     int gcur = 0;                   // f[gcur] holds the populations the graph starts from
     const float* gS = nullptr;      // source pointer the graph was captured with
+    const float* gdB = nullptr;     // space-dependent field pointer the graph was captured with
     int gkey[3] = {0, 0, 0};        // tuning variables at capture (FP32 tile, BF16 tile, collide rows)
 };
 

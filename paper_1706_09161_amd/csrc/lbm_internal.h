@@ -80,6 +80,12 @@ struct CollideConsts {
     float R[kMaxQ * kMaxQ]; // M^-1 Lambda M (BGK: I / lambda), row-major
     float wSdt[kMaxQ];      // w_i dt (multiplies S)
     float c_wall;
+    // Space-dependent coefficients (both null, or both set):
+    //   dB: d(d+1)/2 node fields, the upper triangle (row by row) of
+    //       lambda-bar(x)^-1 - lambda-bar^-1, added to the flux block of Lambda;
+    //   Cw: one node field, the Dirichlet value of every wall node.
+    const float* dB;
+    const float* Cw;
 };
 
 // Kernel launchers (host functions).  All return a hipError_t.
@@ -100,6 +106,7 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
 hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f,
                                    hipStream_t s);
 hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t count, float v, hipStream_t s);
 hipError_t launch_moment(const CollideConsts& cc, const float* f, float* C, hipStream_t s);
 hipError_t launch_nonfinite_check(const float* C, int64_t nodes, int* flag, hipStream_t s);
 bool have_bf16x3();

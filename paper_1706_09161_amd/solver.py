@@ -156,6 +156,23 @@ class LbmFade:
         ptr, dev, keep = self._in(S, self.nodes)
         L.check(L.lib().lbm_fade_set_source(self._h, ptr, dev, _stream_ptr(stream)))
 
+    def set_diffusion(self, D, stream=None):
+        """Space-dependent diffusion tensor: D of shape (d, d, *grid shape), or None
+        for the constant tensor of the handle (MRT only)."""
+        if D is None:
+            L.check(L.lib().lbm_fade_set_diffusion(self._h, None, 0, _stream_ptr(stream)))
+            return
+        ptr, dev, keep = self._in(D, self.dim * self.dim * self.nodes)
+        L.check(L.lib().lbm_fade_set_diffusion(self._h, ptr, dev, _stream_ptr(stream)))
+
+    def set_wall(self, Cw, stream=None):
+        """Dirichlet value of every wall node (a node field), or None for c_wall."""
+        if Cw is None:
+            L.check(L.lib().lbm_fade_set_wall(self._h, None, 0, _stream_ptr(stream)))
+            return
+        ptr, dev, keep = self._in(Cw, self.nodes)
+        L.check(L.lib().lbm_fade_set_wall(self._h, ptr, dev, _stream_ptr(stream)))
+
     def step(self, n: int = 1, stream=None):
         L.check(L.lib().lbm_fade_step(self._h, int(n), _stream_ptr(stream)))
 

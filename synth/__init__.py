@@ -200,3 +200,30 @@ class PowerLawProblem:
 
     def source(self, t: float) -> np.ndarray:
         return -math.exp(-t) * ((self.dim + 1) * self.base + self.extra)
+
+
+def random_tensor_field(cfg: dict, seed: int, zero_fraction: float = 0.05) -> np.ndarray:
+    """Seeded field of symmetric positive semi-definite d x d tensors, shape
+    (d, d, *shape): diagonal entries in [0.02, 0.3], off-diagonal entries
+    scaled to keep every node's tensor definite, and a fraction of nodes with
+    D = 0 (the semi-definite limit).  Values are FP32-representable."""
+    d = cfg["dim"]
+    shp = shape(cfg)
+    rng = np.random.default_rng(seed)
+    diag = rng.uniform(0.02, 0.3, (d,) + shp)
+    D = np.zeros((d, d) + shp)
+    for a in range(d):
+        D[a, a] = diag[a]
+    for a in range(d):
+        for b in range(a + 1, d):
+            r = rng.uniform(-0.45, 0.45, shp) / max(d - 1, 1)
+            D[a, b] = D[b, a] = r * np.sqrt(diag[a] * diag[b])
+    zero = rng.random(shp) < zero_fraction
+    D[:, :, zero] = 0.0
+    return D.astype(np.float32).astype(np.float64)
+
+
+def random_wall_values(cfg: dict, seed: int) -> np.ndarray:
+    """Seeded field of Dirichlet values in [-0.5, 1] (only wall entries matter)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-0.5, 1.0, shape(cfg)).astype(np.float32).astype(np.float64)
