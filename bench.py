@@ -217,6 +217,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the full-length accuracy runs")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the launch sequence profiled by rocprofv3 (copy calibration, GEMM, steps); no JSON")
     args = ap.parse_args()
@@ -304,11 +305,12 @@ def main():
                               "gemm_us_per_step": b["gemm_s"] * 1e6,
                               "gemm_mfma_TFLOPs_3terms": round(bach, 3),
                               "gemm_frac_of_bf16_peak": round(bach / PEAK["bf16_mfma_TFLOPs"], 4)}
-    try:
-        log("adjoint / forward")
-        line["adjoint_over_fwd"] = adjoint_ratio(torch, LbmFade, synth)
-    except Exception as e:  # reported, never fatal for the throughput line
-        line["adjoint_over_fwd"] = {"value": None, "error": str(e)}
+    if not args.no_adjoint:
+        try:
+            log("adjoint / forward")
+            line["adjoint_over_fwd"] = adjoint_ratio(torch, LbmFade, synth)
+        except Exception as e:  # reported, never fatal for the throughput line
+            line["adjoint_over_fwd"] = {"value": None, "error": str(e)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(cfg)
