@@ -41,7 +41,7 @@ class Problem(ctypes.Structure):
         ("dim", ctypes.c_int32),
         ("n", ctypes.c_int32 * 3),
         ("collision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flux_form", ctypes.c_int32),
         ("dx", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("alpha", ctypes.c_double * 3),
@@ -115,6 +115,7 @@ def make_problem(cfg: dict) -> Problem:
     for mu in range(3):
         P.n[mu] = int(cfg["n"][mu]) if mu < d else 1
     P.collision = {"BGK": 0, "MRT": 1}[cfg.get("collision", "MRT")]
+    P.flux_form = {"rl": 0, "caputo": 1}[cfg.get("flux_form", "rl")]
     P.dx = float(cfg.get("dx", 1.0))
     P.dt = float(cfg.get("dt", 1.0))
     for mu in range(d):

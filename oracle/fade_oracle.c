@@ -22,7 +22,8 @@
  * repeated at its point of use):
  *   - grid size n[mu] counts nodes per axis INCLUDING both wall nodes, so the
  *     paper's N_mu = n[mu] - 1 and node indices run 0..N_mu (Sec. 2.4);
- *   - c+_{00} and c-_{NN}: the "l = n" branch applies, value 1 (Sec. 2.4);
+ *   - c+_{00} and c-_{NN} (integrals over an empty interval): 0^gamma, the value
+ *     the exactness rule for constants gives at n = 0 (Sec. 2.4);
  *   - a wall node with several unknown populations (2D corners, 3D edges and
  *     corners) shares the Dirichlet deficit equally among them (Sec. 2.5);
  *   - initial populations are the equilibrium of the initial concentration,
@@ -52,7 +53,7 @@ typedef struct {
     int32_t dim;        /* 2 (D2Q5) or 3 (D3Q7) */
     int32_t n[3];       /* nodes per axis, both wall nodes included */
     int32_t collision;  /* 0 = BGK, 1 = MRT */
-    int32_t reserved;
+    int32_t flux_form;  /* 0 = equation (Fg), 1 = the Caputo-type variant (Fg2) */
     double dx, dt;
     double alpha[3];    /* in (1, 2] */
     double p[3];        /* in [0, 1] */
@@ -111,12 +112,16 @@ int fo_lattice(int32_t dim, int32_t* Q, int32_t* e /* 7x3 */, double* w /* 7 */,
 /* ------------------------------------------------------------------------ */
 /* Trapezoidal product-rule coefficients for the left fractional integral,
  * equation (c+) of Sec. 2.4 (after Diethelm et al.).  Defined for 0 <= l <= n;
- * zero outside the summation range.  Reading: at l = n = 0 both the l = 0 and
- * the l = n branches apply; the l = n branch is taken (value 1), which keeps
- * the gamma = 0 operator equal to the identity. */
+ * zero outside the summation range.  Reading at l = n = 0, where the printed
+ * branches do not apply (the l = 0 branch needs (n - 1)^(gamma+1) at n = 0):
+ * the integral over the empty interval [x_0, x_0] vanishes, and the weights
+ * integrate constants exactly, sum_l c+_{ln} = (1 + gamma) n^gamma, which at
+ * n = 0 gives c+_{00} = 0^gamma: 0 for gamma > 0, 1 for gamma = 0 (the
+ * identity operator of alpha = 2). */
 double fo_cplus(int64_t l, int64_t n, double gamma)
 {
     if (l < 0 || l > n) return 0.0;
+    if (n == 0) return pow(0.0, gamma);
     if (l == n) return 1.0;
     const double gp1 = gamma + 1.0;
     if (l == 0)
@@ -125,10 +130,12 @@ double fo_cplus(int64_t l, int64_t n, double gamma)
 }
 
 /* Coefficients for the right fractional integral, equation (c-) of Sec. 2.4.
- * Defined for n <= l <= N; zero outside.  Same reading at l = n = N. */
+ * Defined for n <= l <= N; zero outside.  Same reading at l = n = N:
+ * c-_{NN} = 0^gamma. */
 double fo_cminus(int64_t l, int64_t n, int64_t N, double gamma)
 {
     if (l < n || l > N) return 0.0;
+    if (n == N) return pow(0.0, gamma);
     if (l == n) return 1.0;
     const double gp1 = gamma + 1.0;
     if (l == N)
@@ -171,6 +178,7 @@ static int validate(const fo_problem* P)
         if (!(P->g[mu] > 0.0)) return FO_EINVAL;
     }
     if (P->collision != 0 && P->collision != 1) return FO_EINVAL;
+    if (P->flux_form != 0 && P->flux_form != 1) return FO_EINVAL;
     return FO_OK;
 }
 
@@ -228,6 +236,22 @@ static double phi_on_line(const coeff_table* T, const double* line, int64_t n,
     return p * (pref * splus) + (1.0 - p) * (pref * sminus);
 }
 
+/* The Caputo-type variant of the flux, equation (Fg2) of Sec. 3.5, puts the
+ * derivative inside the fractional integrals.  Integration by parts
+ * (equations (PSRLdD-a), (PSRLdD-b)) turns its equilibrium term, equation
+ * (CoeffA_FADE3DPS), into the term of (Fg) minus the boundary values of the
+ * line (the ends of the integration intervals on the box boundary):
+ *   p g C(y_0) (x_n - x_0)^(2-alpha) / Gamma(3-alpha)
+ *     + (1 - p) g C(y_N) (x_N - x_n)^(2-alpha) / Gamma(3-alpha),
+ * with x_n - x_0 = n dx and x_N - x_n = (N - n) dx.  0^0 = 1 (alpha = 2). */
+static double variant_boundary_term(double c0, double cN, int64_t n, int64_t N, double p, double g, double alpha,
+                                    double dx)
+{
+    const double G = tgamma(3.0 - alpha);
+    return p * g * c0 * pow((double)n * dx, 2.0 - alpha) / G +
+           (1.0 - p) * g * cN * pow((double)(N - n) * dx, 2.0 - alpha) / G;
+}
+
 int fo_phi(const fo_problem* P, const double* C, double* Phi)
 {
     int rc = validate(P);
@@ -255,8 +279,13 @@ int fo_phi(const fo_problem* P, const double* C, double* Phi)
                      * (stride < s) and the index above mu */
                     const int64_t base = (q % s) + (q / s) * s * len;
                     for (int64_t l = 0; l < len; ++l) line[l] = C[base + l * s];
-                    for (int64_t n = 0; n < len; ++n)
-                        out[base + n * s] = phi_on_line(&T, line, n, P->p[mu], P->g[mu], pref);
+                    for (int64_t n = 0; n < len; ++n) {
+                        double v = phi_on_line(&T, line, n, P->p[mu], P->g[mu], pref);
+                        if (P->flux_form == 1)
+                            v -= variant_boundary_term(line[0], line[N], n, N, P->p[mu], P->g[mu], P->alpha[mu],
+                                                       P->dx);
+                        out[base + n * s] = v;
+                    }
                 }
                 free(line);
             }
@@ -288,7 +317,10 @@ int fo_phi_at(const fo_problem* P, const double* C, const int64_t* which, int64_
             double splus = 0.0, sminus = 0.0;
             for (int64_t l = 0; l <= n; ++l) splus += fo_cplus(l, n, gamma) * (g * C[base + l * s]);
             for (int64_t l = n; l <= N; ++l) sminus += fo_cminus(l, n, N, gamma) * (g * C[base + l * s]);
-            Phi[(int64_t)mu * count + k] = p * (pref * splus) + (1.0 - p) * (pref * sminus);
+            double v = p * (pref * splus) + (1.0 - p) * (pref * sminus);
+            if (P->flux_form == 1)
+                v -= variant_boundary_term(C[base], C[base + N * s], n, N, p, g, P->alpha[mu], P->dx);
+            Phi[(int64_t)mu * count + k] = v;
         }
     }
     return FO_OK;
@@ -831,7 +863,8 @@ int fo_threads(void)
 /* Fractional-term data of one axis for the adjoint: coefficient tables and scalars. */
 typedef struct {
     coeff_table T;
-    double pref, p, g;
+    double pref, p, g, alpha, dx;
+    int flux_form;
     int64_t len, s;
 } axis_data;
 
@@ -843,11 +876,16 @@ static int axis_prepare(const fo_problem* P, int mu, axis_data* A)
     A->pref = pow(P->dx, gamma) / tgamma(2.0 + gamma);
     A->p = P->p[mu];
     A->g = P->g[mu];
+    A->alpha = P->alpha[mu];
+    A->dx = P->dx;
+    A->flux_form = P->flux_form;
     return make_table(A->len - 1, gamma, &A->T);
 }
 
 /* Adjoint of Phi_mu = K_mu C along every line of axis mu: Cbar += K^T Phibar,
- * and dL/dp_mu += <Phibar, pref g (W+ C - W- C)>. */
+ * and dL/dp_mu += <Phibar, pref g (W+ C - W- C)>; with the Caputo-type
+ * variant also the transposed boundary terms (they reach the two wall nodes
+ * of the line) and their p-derivative. */
 static int phi_adjoint_axis(const fo_problem* P, const axis_data* A, int mu, const double* C, const double* Phibar,
                             double* Cbar, double* pbar)
 {
@@ -884,6 +922,13 @@ static int phi_adjoint_axis(const fo_problem* P, const axis_data* A, int mu, con
                         sminus += A->T.cm[n * m + l] * (A->g * c[l]);
                     }
                     line_p += pb[n] * A->pref * (splus - sminus);
+                    if (A->flux_form == 1) {
+                        const double bp = variant_boundary_term(1.0, 0.0, n, N, 1.0, A->g, A->alpha, A->dx);
+                        const double bm = variant_boundary_term(0.0, 1.0, n, N, 0.0, A->g, A->alpha, A->dx);
+                        cb[0] -= pb[n] * A->p * bp;
+                        cb[N] -= pb[n] * (1.0 - A->p) * bm;
+                        line_p -= pb[n] * (bp * c[0] - bm * c[N]);
+                    }
                 }
                 acc_p += line_p;
                 for (int64_t l = 0; l < len; ++l) Cbar[base + l * s] += cb[l];

@@ -227,3 +227,48 @@ def random_wall_values(cfg: dict, seed: int) -> np.ndarray:
     """Seeded field of Dirichlet values in [-0.5, 1] (only wall entries matter)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-0.5, 1.0, shape(cfg)).astype(np.float32).astype(np.float64)
+
+
+class CaputoPowerLawProblem:
+    """Exact-solution workload of the Caputo-type flux variant (Sec. 3.5,
+    equations (Fg2), (SourceTerm_PS)): on [0, 1]^d with p = 1, u = 0, g = 1,
+    constant diagonal D = diag(D_mu),
+        C(x, t) = e^-t prod_mu (x_mu^beta_mu + a_mu),
+        S(x, t) = -C - e^-t sum_mu D_mu Gamma(beta_mu + 1) / Gamma(beta_mu + 1 - alpha_mu)
+                        x_mu^(beta_mu - alpha_mu) prod_{nu != mu} (x_nu^beta_nu + a_nu),
+    because I+^(2-alpha) d/dx x^beta = Gamma(beta + 1) / Gamma(beta + 2 - alpha)
+    x^(beta + 1 - alpha).  beta = alpha is the paper's case (the source then
+    has the constant factors Gamma(alpha_mu + 1)).  Problem data, not the method."""
+
+    def __init__(self, dim: int, n: int, dt: float, *, alpha=None, a=None, beta=None, Dmu=None,
+                 tau_free: float = 1.0):
+        self.dim = d = dim
+        self.alpha = list(alpha) if alpha is not None else ([1.7, 1.2] if d == 2 else [1.7, 1.2, 1.5])
+        self.a = list(a) if a is not None else ([0.3, 1.2] if d == 2 else [0.3, 1.2, 0.5])
+        self.beta = list(beta) if beta is not None else list(self.alpha)
+        self.Dmu = list(Dmu) if Dmu is not None else [1.0] * d
+        dx = 1.0 / (n - 1)
+        self.cfg = dict(dim=d, n=[n] * d, dx=dx, dt=float(dt), collision="MRT", alpha=self.alpha, p=[1.0] * d,
+                        g=[1.0] * d, u=[0.0] * d, D=np.diag(self.Dmu).tolist(), tau_free=[tau_free] * 4, tau0=1.0,
+                        c_wall=0.0, flux_form="caputo", steps=0, name=f"caputo_{d}d_{n}")
+        x = np.arange(n, dtype=np.float64) * dx
+        grids = np.meshgrid(*([x] * d), indexing="ij")
+        X = list(reversed(grids))
+        fac = [X[mu] ** self.beta[mu] + self.a[mu] for mu in range(d)]
+        self.base = np.ones(X[0].shape)
+        for mu in range(d):
+            self.base = self.base * fac[mu]
+        self.flux_div = np.zeros(self.base.shape)
+        for mu in range(d):
+            b, al = self.beta[mu], self.alpha[mu]
+            term = self.Dmu[mu] * math.gamma(b + 1) / math.gamma(b + 1 - al) * X[mu] ** (b - al)
+            for nu in range(d):
+                if nu != mu:
+                    term = term * fac[nu]
+            self.flux_div += term
+
+    def exact(self, t: float) -> np.ndarray:
+        return math.exp(-t) * self.base
+
+    def source(self, t: float) -> np.ndarray:
+        return -math.exp(-t) * (self.base + self.flux_div)

@@ -91,3 +91,34 @@ def test_parameter_gradients_match_central_differences(oracle_lib, dim, n, colli
             fd = _fd(oracle_lib, cfg, C0, S, gC, steps, pert, h)
             expect = g["D"][a, b] * (1 if a == b else 2)
             assert expect == pytest.approx(fd, rel=1e-6, abs=1e-10), (a, b)
+
+
+@pytest.mark.parametrize("dim,n", [(2, [11, 10]), (3, [6, 7, 5])])
+def test_caputo_variant_adjoint(oracle_lib, dim, n):
+    """The Caputo-type flux (Sec. 3.5) adds boundary terms to the fractional
+    term that reach the wall values of each line: with a non-zero wall value
+    the affine identity for C0 and the D, u, p gradients against central
+    differences."""
+    cfg, C0, S, gC = _problem(dim, n, seed=73, c_wall=0.3)
+    cfg["flux_form"] = "caputo"
+    steps = 5
+    g = oracle_lib.adjoint(cfg, C0, steps, gC, S=S)
+    rng = np.random.default_rng(4)
+    delta = rng.standard_normal(C0.shape)
+    dL = oracle_lib.loss(cfg, C0 + delta, steps, gC, S=S) - oracle_lib.loss(cfg, C0, steps, gC, S=S)
+    assert float(np.sum(g["dC0"] * delta)) == pytest.approx(dL, rel=1e-11)
+    h = 1e-5
+    for k in range(dim):
+        for key in ("u", "p"):
+            def f(c, dh, key=key, k=k):
+                v = list(c[key])
+                v[k] = v[k] + dh
+                c[key] = v
+            fd = _fd(oracle_lib, cfg, C0, S, gC, steps, f, h)
+            assert g[key][k] == pytest.approx(fd, rel=1e-7, abs=1e-10), (key, k)
+    D0 = np.array(cfg["D"])
+
+    def pert(c, dh):
+        c["D"] = (D0 + dh * np.eye(dim)).tolist()
+    fd = _fd(oracle_lib, cfg, C0, S, gC, steps, pert, h)
+    assert np.trace(g["D"]) == pytest.approx(fd, rel=1e-6)

@@ -82,13 +82,13 @@ def test_cplus_equals_hat_function_quadrature(oracle_lib, gamma):
 def test_cplus_sum_and_first_moment_rules(oracle_lib, gamma):
     """Exactness on constants and on linear functions (power law of
     equation (derfracpuissce) with a = 0 and a = 1): sum_l c+_{ln} = (1+gamma) n^gamma
-    and sum_l l c+_{ln} = n^(gamma+1) for n >= 1.  (At n = 0 the reading c+_{00} = 1
-    is taken instead.)"""
-    for n in range(1, 61):
+    and sum_l l c+_{ln} = n^(gamma+1), n >= 0 (at n = 0 the integral is over an
+    empty interval: c+_{00} = 0^gamma, 1 only for gamma = 0)."""
+    for n in range(0, 61):
         c = np.array([oracle_lib.cplus(l, n, gamma) for l in range(n + 1)])
-        assert c.sum() == pytest.approx((1 + gamma) * n**gamma, rel=1e-12)
-        assert (np.arange(n + 1) * c).sum() == pytest.approx(n ** (gamma + 1), rel=1e-12)
-    assert oracle_lib.cplus(0, 0, gamma) == 1.0
+        assert c.sum() == pytest.approx((1 + gamma) * float(n) ** gamma, rel=1e-12, abs=1e-300)
+        assert (np.arange(n + 1) * c).sum() == pytest.approx(float(n) ** (gamma + 1), rel=1e-12)
+    assert oracle_lib.cplus(0, 0, gamma) == (1.0 if gamma == 0.0 else 0.0)
 
 
 @pytest.mark.parametrize("gamma", GAMMAS)
