@@ -88,8 +88,17 @@ typedef struct {
     int32_t collision;  /* LBM_BGK (needs isotropic D) or LBM_MRT */
     int32_t precision;  /* LBM_FP32, LBM_BF16X3 or LBM_FP32_SIMT */
     int32_t nonfinite_check_every; /* 0 = off; else check C every k steps inside lbm_fade_step */
-    int32_t reserved;
+    int32_t flux_form;  /* LBM_FLUX_RL: the dispersive flux of equation (Fg) (derivative of the
+                           fractional integrals); LBM_FLUX_CAPUTO: the Caputo-type flux of equation
+                           (Fg2), Sec. 3.5 (fractional integrals of the derivative), whose
+                           equilibrium (CoeffA_FADE3DPS) subtracts, per axis, p g C(x_0)
+                           (x - x_0)^(2-alpha) / Gamma(3-alpha) and (1-p) g C(x_N)
+                           (x_N - x)^(2-alpha) / Gamma(3-alpha) from the fractional term, with
+                           x_0, x_N the wall nodes ending the line (uniform C is then an
+                           equilibrium) */
 } lbm_params;
+
+enum { LBM_FLUX_RL = 0, LBM_FLUX_CAPUTO = 1 };
 
 /* Create a solver on the current HIP device.  Computes in FP64 on the host:
  * the relaxation times lambda-bar = D dt/(e^2 dx^2) + Id/2 (equation (D_ab);
@@ -98,9 +107,11 @@ typedef struct {
  * c+-_{ln}(gamma_mu) of equations (c+), (c-) scaled by dx^gamma/Gamma(2+gamma),
  * as one Toeplitz generator per axis plus two boundary columns.
  * Allocates the device state (two population buffers, C, Phi, weights).
+ * The product-rule integrals over the empty intervals at the ends of a line
+ * (c+_{00}, c-_{NN}) are 0^gamma (constants stay integrated exactly there).
  * Errors: LBM_EINVAL for alpha outside (1,2], p outside [0,1], g <= 0, D not SPD
  * (or not isotropic for BGK), tau_free <= 1/2, tau0 <= 0, n < 3, lattice != 2*dim+1,
- * unknown collision/precision; LBM_EDEVICE if the current device is not gfx950.
+ * unknown collision/precision/flux_form; LBM_EDEVICE if the current device is not gfx950.
  * On error *out is set to NULL. */
 LBM_API int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* params, lbm_fade_t* out);
 

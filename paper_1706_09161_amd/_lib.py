@@ -11,6 +11,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1,
 LBM_D2Q5, LBM_D3Q7 = 5, 7
 LBM_BGK, LBM_MRT = 0, 1
 LBM_FP32, LBM_BF16X3, LBM_FP32_SIMT = 0, 1, 2
+LBM_FLUX_RL, LBM_FLUX_CAPUTO = 0, 1
 
 ERROR_NAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM", LBM_EDEVICE: "LBM_EDEVICE",
                LBM_ENONFINITE: "LBM_ENONFINITE", LBM_ESTATE: "LBM_ESTATE"}
@@ -39,7 +40,7 @@ class lbm_params(ctypes.Structure):
         ("collision", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("nonfinite_check_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flux_form", ctypes.c_int32),
     ]
 
 

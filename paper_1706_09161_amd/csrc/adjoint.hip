@@ -404,8 +404,26 @@ bool build_ops(lbm_fade* h, AdjointState* A)
             else tP = 0.0;
             gP[dd + N] = (float)tP;
         }
-        for (int j = 1; j <= N; ++j) pc0[j] = (float)(s * (C.cp0[j] - C.a[j]));
-        for (int j = 0; j <= N - 1; ++j) pcN[j] = (float)(-s * (C.cmN[j] - C.a[N - j]));
+        // d(corr0)/dp and d(corrN)/dp of the forward operator (make_axis_weights), FP64
+        {
+            const double gm = 2.0 - h->params.alpha[mu];
+            const double empty = pow(0.0, gm);  // c+_{00} = c-_{NN}
+            std::vector<double> d0(n, 0.0), dN(n, 0.0);
+            for (int j = 1; j <= N; ++j) d0[j] = s * (C.cp0[j] - C.a[j]);
+            for (int j = 0; j <= N - 1; ++j) dN[j] = -s * (C.cmN[j] - C.a[N - j]);
+            d0[0] = s * (empty - 1.0);
+            dN[N] = -s * (empty - 1.0);
+            if (h->params.flux_form == 1) {
+                for (int j = 0; j <= N; ++j) {
+                    d0[j] -= s * (1.0 + gm) * pow((double)j, gm);
+                    dN[j] += s * (1.0 + gm) * pow((double)(N - j), gm);
+                }
+            }
+            for (int j = 0; j <= N; ++j) {
+                pc0[j] = (float)d0[j];
+                pcN[j] = (float)dN[j];
+            }
+        }
         AxisOp& T = A->opsT[mu];
         T.n = n;
         T.lower_only = h->ops[mu].upper_only;

@@ -159,13 +159,20 @@ namespace {
 // ---------------------------------------------------------------------------
 // Forward operator of one axis from the product-rule coefficients:
 // K[j][k] = s (p c+_{kj} + (1-p) c-_{kj}) = T(j - k) + [k == 0] corr0[j] + [k == N] corrN[j].
+// The integrals over the empty intervals (c+_{00}, c-_{NN}) are 0^gamma: the
+// value that keeps constants integrated exactly at j = 0 and j = N.
+// flux_form 1 (the Caputo-type flux (Fg2) of Sec. 3.5): integration by parts
+// (equations (PSRLdD-a), (PSRLdD-b), (CoeffA_FADE3DPS)) subtracts
+// g C(x_0) (j dx)^gamma / Gamma(1 + gamma) (times p) and
+// g C(x_N) ((N - j) dx)^gamma / Gamma(1 + gamma) (times 1 - p), a change of the
+// two boundary columns only: s (1 + gamma) j^gamma in units of s.
 struct AxisWeights {
     std::vector<double> T;      // T(d) at d + N, d in [-N, N]
     std::vector<double> corr0;  // n
     std::vector<double> corrN;  // n
 };
 
-AxisWeights make_axis_weights(int n, double gamma, double p, double g, double dx)
+AxisWeights make_axis_weights(int n, double gamma, double p, double g, double dx, int flux_form)
 {
     const int N = n - 1;
     const lbm::AxisCoeffs A = lbm::axis_coeffs(n, gamma, g, dx);
@@ -183,6 +190,15 @@ AxisWeights make_axis_weights(int n, double gamma, double p, double g, double dx
     }
     for (int j = 1; j <= N; ++j) W.corr0[j] = s * p * A.cp0[j] - W.T[j + N];
     for (int j = 0; j <= N - 1; ++j) W.corrN[j] = s * (1.0 - p) * A.cmN[j] - W.T[(j - N) + N];
+    const double empty = pow(0.0, gamma);  // c+_{00} = c-_{NN}; T(0) holds 1 there
+    W.corr0[0] = s * p * (empty - 1.0);
+    W.corrN[N] = s * (1.0 - p) * (empty - 1.0);
+    if (flux_form == 1) {
+        for (int j = 0; j <= N; ++j) {
+            W.corr0[j] -= s * p * (1.0 + gamma) * pow((double)j, gamma);
+            W.corrN[j] -= s * (1.0 - p) * (1.0 + gamma) * pow((double)(N - j), gamma);
+        }
+    }
     return W;
 }
 
@@ -230,6 +246,7 @@ int validate(const lbm_grid* grid, int lattice, const lbm_params* P)
         return fail(LBM_EINVAL, "the split-BF16 kernel is not part of this build");
     if (P->nonfinite_check_every < 0) return fail(LBM_EINVAL, "nonfinite_check_every must be >= 0");
     if (!isfinite(P->c_wall)) return fail(LBM_EINVAL, "c_wall must be finite");
+    if (P->flux_form != 0 && P->flux_form != 1) return fail(LBM_EINVAL, "flux_form must be 0 or 1");
     return LBM_OK;
 }
 
@@ -564,7 +581,8 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
     std::vector<AxisWeights> W(d);
     for (int mu = 0; mu < d; ++mu) {
         const size_t n = (size_t)grid->n[mu];
-        W[mu] = make_axis_weights((int)n, 2.0 - params->alpha[mu], params->p[mu], params->g[mu], grid->dx);
+        W[mu] = make_axis_weights((int)n, 2.0 - params->alpha[mu], params->p[mu], params->g[mu], grid->dx,
+                                  params->flux_form);
         bytes += r256(sizeof(float) * (2 * n - 1)) + 2 * r256(sizeof(float) * n) +
                  2 * r256(sizeof(uint16_t) * (2 * n - 1)) + 2 * r256(sizeof(uint32_t) * lbm::pw_len_of((int)n));
     }

@@ -15,6 +15,7 @@ from . import _lib as L
 
 _COLLISION = {"BGK": L.LBM_BGK, "MRT": L.LBM_MRT}
 _PRECISION = {"fp32": L.LBM_FP32, "bf16x3": L.LBM_BF16X3, "fp32_simt": L.LBM_FP32_SIMT}
+_FLUX_FORM = {"rl": L.LBM_FLUX_RL, "caputo": L.LBM_FLUX_CAPUTO}
 
 
 def _torch():
@@ -48,7 +49,7 @@ class LbmFade:
 
     def __init__(self, dim: int, n, *, alpha, p, D, g=None, u=None, dx: float = 1.0, dt: float = 1.0,
                  tau_free=None, tau0: float = 1.0, c_wall: float = 0.0, collision: str = "MRT",
-                 precision: str = "fp32", nonfinite_check_every: int = 0):
+                 precision: str = "fp32", nonfinite_check_every: int = 0, flux_form: str = "rl"):
         lib = L.lib()
         self.dim = int(dim)
         self.n = [int(v) for v in n][: self.dim]
@@ -81,6 +82,7 @@ class LbmFade:
         P.collision = _COLLISION[collision]
         P.precision = _PRECISION[precision]
         P.nonfinite_check_every = int(nonfinite_check_every)
+        P.flux_form = _FLUX_FORM[flux_form]
         h = ctypes.c_void_p()
         L.check(lib.lbm_fade_create(ctypes.byref(grid), self.Q, ctypes.byref(P), ctypes.byref(h)))
         self._h = h
@@ -93,7 +95,7 @@ class LbmFade:
         return cls(d, cfg["n"][:d], alpha=cfg["alpha"], p=cfg["p"], D=cfg["D"], g=cfg.get("g"), u=cfg.get("u"),
                    dx=cfg.get("dx", 1.0), dt=cfg.get("dt", 1.0), tau_free=cfg.get("tau_free"),
                    tau0=cfg.get("tau0", 1.0), c_wall=cfg.get("c_wall", 0.0), collision=cfg.get("collision", "MRT"),
-                   precision=precision, **kw)
+                   precision=precision, flux_form=cfg.get("flux_form", "rl"), **kw)
 
     # -- lifetime -------------------------------------------------------------
     def close(self):

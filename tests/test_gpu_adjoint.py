@@ -32,18 +32,20 @@ def _rel(a, b):
 
 
 CASES = [
-    (2, [37, 29], "MRT", 0.0, 12, 5),
-    (2, [33, 40], "BGK", 0.2, 10, 4),
-    (3, [14, 11, 9], "MRT", 0.0, 8, 3),
-    (3, [9, 12, 10], "BGK", 0.0, 7, 7),
-    (2, [3, 4], "MRT", 0.3, 5, 2),
+    (2, [37, 29], "MRT", 0.0, 12, 5, "rl"),
+    (2, [33, 40], "BGK", 0.2, 10, 4, "rl"),
+    (3, [14, 11, 9], "MRT", 0.0, 8, 3, "rl"),
+    (3, [9, 12, 10], "BGK", 0.0, 7, 7, "rl"),
+    (2, [3, 4], "MRT", 0.3, 5, 2, "rl"),
+    (2, [37, 29], "MRT", 0.3, 12, 5, "caputo"),   # Caputo-type flux (Sec. 3.5), non-zero walls
+    (3, [14, 11, 9], "BGK", 0.2, 8, 3, "caputo"),
 ]
 
 
-@pytest.mark.parametrize("dim,n,collision,c_wall,steps,K", CASES)
-def test_adjoint_matches_oracle(dim, n, collision, c_wall, steps, K):
-    print(f"[gpu-adjoint] dim={dim} n={n} {collision} steps={steps} K={K}", flush=True)
-    cfg = synth.small(dim, n, seed=81, collision=collision, with_source=True, c_wall=c_wall)
+@pytest.mark.parametrize("dim,n,collision,c_wall,steps,K,flux_form", CASES)
+def test_adjoint_matches_oracle(dim, n, collision, c_wall, steps, K, flux_form):
+    print(f"[gpu-adjoint] dim={dim} n={n} {collision} steps={steps} K={K} {flux_form}", flush=True)
+    cfg = synth.small(dim, n, seed=81, collision=collision, with_source=True, c_wall=c_wall, flux_form=flux_form)
     C0 = synth.initial_C(cfg).astype(np.float32)
     S = synth.source(cfg).astype(np.float32)
     rng = np.random.default_rng(5)
