@@ -272,3 +272,26 @@ class CaputoPowerLawProblem:
 
     def source(self, t: float) -> np.ndarray:
         return -math.exp(-t) * (self.base + self.flux_div)
+
+
+# ---------------------------------------------------------------------------
+# High-Peclet stability workload of Sec. 3.3: Omega = [0, 2] x [0, 1],
+# dx = 0.01 (201 x 101 nodes), dt = 8e-4, D = 2e-3 Id (BGK relaxation time
+# 0.548), p = 1/2, g = 1, u = (u1, 0), homogeneous Dirichlet walls, and the
+# paper's Gaussian hill (Gaussian_IC_3D) with sigma_0 = 0.002, C_0 = 5 centred
+# at (0.5, 0.5).  alpha = 2 is the advection-diffusion case.
+
+def stability_config(alpha: float, u1: float, collision: str, tau_free: float = 1.0) -> dict:
+    return dict(dim=2, n=[201, 101], dx=0.01, dt=8e-4, alpha=[alpha, alpha], p=[0.5, 0.5], g=[1.0, 1.0],
+                D=[[2e-3, 0.0], [0.0, 2e-3]], u=[u1, 0.0], collision=collision, tau_free=[tau_free] * 4,
+                tau0=1.0, c_wall=0.0, steps=1250,
+                name=f"stability_a{alpha}_u{u1}_{collision}_{tau_free}")
+
+
+def paper_gaussian(cfg: dict, center, sigma0: float = 0.002, C0: float = 5.0) -> np.ndarray:
+    """Equation (Gaussian_IC_3D) sampled at the nodes (physical coordinates)."""
+    d = cfg["dim"]
+    dx = cfg["dx"]
+    X = _coords(cfg)
+    r2 = sum((X[mu] * dx - center[mu]) ** 2 for mu in range(d))
+    return C0 / (2 * math.pi * sigma0 ** 2) ** (d / 2) * np.exp(-0.5 * r2 / sigma0 ** 2)
