@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfade_oracle.so")
-_SOURCES = ["fade_oracle.c"]
+_SOURCES = ["fade_oracle.c", "random_walk.c"]
 
 
 def build(force: bool = True) -> str:
@@ -314,3 +314,128 @@ def adjoint(cfg: dict, C0: np.ndarray, nsteps: int, gC: np.ndarray, S: np.ndarra
 def loss(cfg: dict, C0: np.ndarray, nsteps: int, gC: np.ndarray, S: np.ndarray | None = None) -> float:
     """L = <gC, C_n> by the forward oracle."""
     return float(np.sum(np.asarray(gC, np.float64) * run(cfg, C0, nsteps, S=S)))
+
+
+# ---------------------------------------------------------------------------
+# Levy-stable random walk (random_walk.c)
+
+class RWParams(ctypes.Structure):
+    """Mirror of ``fo_rw_params`` in random_walk.c."""
+
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("alpha", ctypes.c_double * 3),
+        ("p", ctypes.c_double * 3),
+        ("D", ctypes.c_double * 3),
+        ("g", ctypes.c_double * 3),
+        ("u", ctypes.c_double * 3),
+        ("dt", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+_rw_sig_done = False
+
+
+def _rw_lib():
+    global _rw_sig_done
+    L = lib()
+    if not _rw_sig_done:
+        R = ctypes.POINTER(RWParams)
+        dp = ctypes.POINTER(ctypes.c_double)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64, u32, u64 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+        sig = {
+            "fo_philox4x32_10": (None, [u32p, u32p, u32p]),
+            "fo_rw_uniforms": (None, [u64, i64, u32, u32, dp]),
+            "fo_stable_from": (ctypes.c_double, [ctypes.c_double] * 4),
+            "fo_stable_draw": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, u64, i64, u32, u32]),
+            "fo_rw_init_gaussian": (ctypes.c_int, [R, dp, ctypes.c_double, i64, i64, dp, u8p]),
+            "fo_rw_walk": (ctypes.c_int, [R, dp, u8p, i64, i64, i64, i64]),
+            "fo_rw_histogram": (ctypes.c_int, [R, dp, u8p, i64, i32p, ctypes.c_double, u32p]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _rw_sig_done = True
+    return L
+
+
+def rw_params(dim, lo, hi, alpha, p, D, g=None, u=None, dt=1e-3, seed=1) -> RWParams:
+    P = RWParams()
+    P.dim = int(dim)
+    for mu in range(dim):
+        P.lo[mu], P.hi[mu] = float(lo[mu]), float(hi[mu])
+        P.alpha[mu], P.p[mu], P.D[mu] = float(alpha[mu]), float(p[mu]), float(D[mu])
+        P.g[mu] = 1.0 if g is None else float(g[mu])
+        P.u[mu] = 0.0 if u is None else float(u[mu])
+    P.dt = float(dt)
+    P.seed = int(seed)
+    return P
+
+
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    _rw_lib().fo_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def rw_uniforms(seed: int, particle: int, step: int, purpose: int):
+    u = np.zeros(2)
+    _rw_lib().fo_rw_uniforms(int(seed), int(particle), int(step), int(purpose), _dp(u))
+    return u
+
+
+def stable_from(alpha, beta, V, W) -> float:
+    return float(_rw_lib().fo_stable_from(float(alpha), float(beta), float(V), float(W)))
+
+
+def stable_draws(alpha, beta, seed, count, step=1, purpose=0) -> np.ndarray:
+    L = _rw_lib()
+    return np.array([L.fo_stable_draw(float(alpha), float(beta), int(seed), k, int(step), int(purpose))
+                     for k in range(int(count))])
+
+
+def rw_init_gaussian(P: RWParams, center, sigma0: float, n: int, first: int = 0):
+    """(x (dim, n), alive (n,)) of particles first .. first + n - 1."""
+    x = np.zeros((P.dim, n))
+    alive = np.zeros(n, np.uint8)
+    c = np.zeros(3)
+    c[: P.dim] = center
+    rc = _rw_lib().fo_rw_init_gaussian(ctypes.byref(P), _dp(c), float(sigma0), int(n), int(first), _dp(x),
+                                       alive.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    _check(rc, "rw_init_gaussian")
+    return x, alive
+
+
+def rw_walk(P: RWParams, x, alive, nsteps: int, first: int = 0, step0: int = 0):
+    """Steps step0 + 1 .. step0 + nsteps; returns new (x, alive)."""
+    x = np.array(x, np.float64, order="C", copy=True)
+    alive = np.array(alive, np.uint8, copy=True)
+    n = alive.size
+    rc = _rw_lib().fo_rw_walk(ctypes.byref(P), _dp(x), alive.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), n,
+                              int(first), int(step0), int(nsteps))
+    _check(rc, "rw_walk")
+    return x, alive
+
+
+def rw_histogram(P: RWParams, x, alive, nodes, dx: float) -> np.ndarray:
+    """Counts of living particles per node, array of shape reversed(nodes)."""
+    x = np.ascontiguousarray(x, np.float64)
+    alive = np.ascontiguousarray(alive, np.uint8)
+    nn = np.zeros(3, np.int32)
+    nn[: P.dim] = nodes
+    counts = np.zeros(int(np.prod(nodes)), np.uint32)
+    rc = _rw_lib().fo_rw_histogram(ctypes.byref(P), _dp(x), alive.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   alive.size, nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(dx),
+                                   counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    _check(rc, "rw_histogram")
+    return counts.reshape(tuple(reversed(list(nodes))))
