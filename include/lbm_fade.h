@@ -201,6 +201,57 @@ typedef struct {
 LBM_API int lbm_fade_adjoint(lbm_fade_t h, int64_t n, int32_t ckpt_every, const float* gC, int32_t on_device,
                      lbm_grads* out, float* dC0, float* dS, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Levy-stable random walk (Sec. 3.1, equations (RW_STABLE), (distri); Sec. 3.2
+ * compares the LB solutions with it).  Particles X in the open box ]lo, hi[
+ * move by X_mu += u_mu dt + (D_mu g_mu)^(1/alpha_mu) (-cos(pi alpha_mu / 2) dt)^(1/alpha_mu)
+ * S(alpha_mu, 2 p_mu - 1) per step and axis, S a stable variable with
+ * characteristic function exp(-|k|^alpha (1 - j beta sign(k) tan(pi alpha / 2)))
+ * (equations (stb), (stbb)) drawn with Weron's formula from two uniforms of
+ * the counter-based generator Philox-4x32-10 at the counter
+ * (particle, step, purpose) under `seed`; a particle not strictly inside the
+ * box after a step is killed (first exit time, observed at the step times)
+ * and stays dead.  The density of the surviving particles approximates the
+ * FADE solution with homogeneous Dirichlet walls.  FP64 throughout; paths do
+ * not depend on how the particles are split across calls (`first`).
+ * Positions are device arrays of dim * n doubles, field-major (x[mu*n + k]);
+ * alive flags one byte per particle (1 = alive).  All pointers are device
+ * pointers ordered on `stream`; calls are asynchronous.  Errors: LBM_EINVAL
+ * for dim outside 1..3, alpha outside (1, 2], p outside [0, 1], D < 0, g <= 0,
+ * lo >= hi, dt <= 0, negative counts. */
+typedef struct {
+    int32_t dim;            /* 1, 2 or 3 */
+    int32_t reserved;
+    double lo[3], hi[3];    /* the box ]lo, hi[ */
+    double alpha[3];        /* stability exponents, (1, 2] */
+    double p[3];            /* skewness weights of the FADE; beta = 2 p - 1 */
+    double D[3];            /* diagonal of the diffusion tensor (>= 0) */
+    double g[3];            /* > 0 */
+    double u[3];            /* velocity */
+    double dt;              /* time step of the walk (the paper uses <= 1e-3) */
+    uint64_t seed;          /* key of the generator */
+} lbm_rw_params;
+
+/* Initial positions of particles first .. first + n - 1: Gaussian hill of
+ * standard deviation sigma0 around center (dim doubles, host) per axis, by
+ * the Box-Muller transform (equation (Gaussian_IC_3D)); alive[k] = 1 if the
+ * position lies in the box. */
+LBM_API int lbm_rw_init_gaussian(const lbm_rw_params* P, const double* center, double sigma0, int64_t n, int64_t first,
+                                 double* x, uint8_t* alive, void* stream);
+
+/* Steps step0 + 1 .. step0 + nsteps (step0 + nsteps < 2^32) of particles
+ * first .. first + n - 1, in place. */
+LBM_API int lbm_rw_walk(const lbm_rw_params* P, double* x, uint8_t* alive, int64_t n, int64_t first, int64_t step0,
+                        int64_t nsteps, void* stream);
+
+/* Counts of the living particles per node of a grid with nodes[mu] nodes per
+ * axis starting at lo with spacing dx (node j collects [lo + (j - 1/2) dx,
+ * lo + (j + 1/2) dx); x fastest), into counts (device, prod(nodes) words,
+ * cleared first; nodes is a host array of dim ints).  A density is
+ * counts / (n dx^dim) times the initial mass. */
+LBM_API int lbm_rw_histogram(const lbm_rw_params* P, const double* x, const uint8_t* alive, int64_t n,
+                             const int32_t* nodes, double dx, uint32_t* counts, void* stream);
+
 /* Message describing the calling thread's most recent failure ("" if none). */
 LBM_API const char* lbm_fade_last_error(void);
 

@@ -20,7 +20,7 @@ ERROR_NAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM", LBM_EDEVICE: 
 EXPORTED = ["lbm_fade_create", "lbm_fade_destroy", "lbm_fade_set_C", "lbm_fade_set_source", "lbm_fade_set_diffusion",
             "lbm_fade_set_wall", "lbm_fade_step",
             "lbm_fade_get_C", "lbm_fade_get_f", "lbm_fade_set_f", "lbm_fade_apply_phi", "lbm_fade_adjoint",
-            "lbm_fade_last_error", "lbm_fade_version"]
+            "lbm_fade_last_error", "lbm_fade_version", "lbm_rw_init_gaussian", "lbm_rw_walk", "lbm_rw_histogram"]
 
 
 class lbm_grid(ctypes.Structure):
@@ -41,6 +41,22 @@ class lbm_params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("nonfinite_check_every", ctypes.c_int32),
         ("flux_form", ctypes.c_int32),
+    ]
+
+
+class lbm_rw_params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("alpha", ctypes.c_double * 3),
+        ("p", ctypes.c_double * 3),
+        ("D", ctypes.c_double * 3),
+        ("g", ctypes.c_double * 3),
+        ("u", ctypes.c_double * 3),
+        ("dt", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -83,6 +99,12 @@ def lib() -> ctypes.CDLL:
         "lbm_fade_apply_phi": (ctypes.c_int, [H, fp, fp, ctypes.c_int32, vp]),
         "lbm_fade_adjoint": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int32, fp, ctypes.c_int32,
                                             ctypes.POINTER(lbm_grads), fp, fp, vp]),
+        "lbm_rw_init_gaussian": (ctypes.c_int, [ctypes.POINTER(lbm_rw_params), ctypes.POINTER(ctypes.c_double),
+                                                ctypes.c_double, ctypes.c_int64, ctypes.c_int64, vp, vp, vp]),
+        "lbm_rw_walk": (ctypes.c_int, [ctypes.POINTER(lbm_rw_params), vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int64, vp]),
+        "lbm_rw_histogram": (ctypes.c_int, [ctypes.POINTER(lbm_rw_params), vp, vp, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_double, vp, vp]),
         "lbm_fade_last_error": (ctypes.c_char_p, []),
         "lbm_fade_version": (ctypes.c_char_p, []),
     }

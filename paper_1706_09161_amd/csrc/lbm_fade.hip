@@ -29,6 +29,15 @@ int fail(int code, const std::string& msg)
     return code;
 }
 
+}  // namespace
+
+namespace lbm {
+// error reporting for the other translation units of the library
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace lbm
+
+namespace {
+
 #define HIP_TRY(expr)                                                                                          \
     do {                                                                                                       \
         hipError_t e_ = (expr);                                                                                \

@@ -110,6 +110,8 @@ hipError_t launch_fill(float* p, int64_t count, float v, hipStream_t s);
 hipError_t launch_moment(const CollideConsts& cc, const float* f, float* C, hipStream_t s);
 hipError_t launch_nonfinite_check(const float* C, int64_t nodes, int* flag, hipStream_t s);
 bool have_bf16x3();
+// Records msg as the calling thread's last error (lbm_fade_last_error) and returns code.
+int set_error(int code, const char* msg);
 // Output tiles of 128 x 128 over all axes (sizes the GEMM launch).
 int64_t big_tiles(const FracLaunch& L);
 // Tile configuration forced through an environment variable (0 = automatic).
