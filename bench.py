@@ -111,12 +111,19 @@ GEMM_SOURCES = [os.path.join(ROOT, "paper_1706_09161_amd", "csrc", f) for f in (
 
 
 def gemm_source_hash() -> str:
+    """Hash of the FP32 GEMM kernel's sources: fractional_gemm.hip and the part
+    of lbm_internal.h that declares the operator structures it reads (up to
+    the collide-stream constants)."""
     import hashlib
 
     h = hashlib.sha256()
     for f in GEMM_SOURCES:
         with open(f, "rb") as fh:
-            h.update(fh.read())
+            data = fh.read()
+        if f.endswith("lbm_internal.h"):
+            cut = data.find(b"// Constants of the fused collide-stream kernel")
+            data = data if cut < 0 else data[:cut]
+        h.update(data)
     return h.hexdigest()[:16]
 
 

@@ -64,3 +64,36 @@ class RandomWalk:
         if not (x.is_cuda and alive.is_cuda and x.dtype == torch.float64 and alive.dtype == torch.uint8
                 and x.is_contiguous() and alive.is_contiguous() and tuple(x.shape) == (self.dim, alive.numel())):
             raise ValueError("x must be a contiguous (dim, n) float64 CUDA tensor and alive a (n,) uint8 one")
+
+
+def main():
+    """Throughput of the walk on the paper's validation 1 (Omega = [0, 2]^2,
+    alpha = (1.5, 1.99), D = 0.5 Id, p = 1/2, dt = 1e-3, t = 0.1): 4e6
+    particles, 100 steps, timed with HIP events on the launch stream."""
+    import argparse
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--particles", type=int, default=4_000_000)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    torch = _torch()
+    W = RandomWalk(2, [0, 0], [2, 2], alpha=[1.5, 1.99], p=[0.5, 0.5], D=[0.5, 0.5], dt=1e-3, seed=2024)
+    stream = torch.cuda.current_stream()
+    best = None
+    for _ in range(args.reps):
+        x, a = W.init_gaussian([1.0, 1.0], 0.05, args.particles)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        W.walk(x, a, args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    draws = args.particles * args.steps * 2
+    print(f"{args.particles} particles x {args.steps} steps: {best:.2f} ms, {draws / best / 1e6:.2f} G stable draws/s, "
+          f"survival {float(a.float().mean()):.5f}")
+
+
+if __name__ == "__main__":
+    main()
