@@ -19,7 +19,8 @@
 // 2D (D2Q5): each wavefront owns a strip of 64 columns starting on a
 // multiple of 64 (its loads and stores are whole 128-byte lines) and marches
 // up the y axis: the collision of row y+1 is computed once, its f*_4 is used
-// for row y and its f*_3 for row y+2.  f*_1 / f*_2 cross columns by lane
+// for row y and its f*_3 for row y+2.  The rows read ahead stop at the first
+// row past the chunk (the last block of a march refills only what it needs).  f*_1 / f*_2 cross columns by lane
 // shuffles; at the strip's two edges lanes 0 and 63 also read the node just
 // outside the strip and compute the one population that crosses (one row of
 // the collision operator).  Every node is collided once (plus 2 halo rows per
@@ -265,12 +266,10 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
     }
     load_row(y0 + D - 1, ring[D - 1]);
     collide_row(ring[0], cur, hcur);
-    for (int yb = y0; yb < y1; yb += D) {
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int y = yb + u;
-            // slot u held row y (collided into cur): refill it with row y + D
-            load_row(y + D, ring[u]);
+    // One output row y from ring slot u: refill the slot with row y + D (when
+    // the chunk still needs that row), collide row y + 1, stream, store.
+    auto row_step = [&](const int u, const int y, const bool refill) __attribute__((always_inline)) {
+            if (refill) load_row(y + D, ring[u]);
             float nxt[5], hnxt;
             collide_row(ring[(u + 1) % D], nxt, hnxt);  // row y + 1
             // pull: f_1 from x-1, f_2 from x+1, f_3 from y-1, f_4 from y+1
@@ -312,7 +311,17 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
 #pragma unroll
             for (int i = 0; i < 5; ++i) cur[i] = nxt[i];
             hcur = hnxt;
-        }
+    };
+    // The chunk needs rows y0 - 1 .. y1: blocks whose refills all stay within
+    // y1 run without a condition; the last block refills only what is needed.
+    int yb = y0;
+    for (; yb + 2 * D - 1 <= y1; yb += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) row_step(u, yb + u, true);
+    }
+    for (; yb < y1; yb += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) row_step(u, yb + u, yb + u + D <= y1);
     }
 }
 
@@ -402,14 +411,13 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
     }
     load_at(z0 + D - 1, ring[D - 1]);
     collide_at(ring[0], cur, hcur);
-    for (int zb = z0; zb < z1; zb += D) {
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int z = zb + u;
+    // One output plane z from ring slot u (the refill condition is the same
+    // for the whole workgroup, so every wave reaches the same barriers).
+    auto plane_step = [&](const int u, const int z, const bool refill) __attribute__((always_inline)) {
             const int par = (z - z0) & 1;
             sh3[par][row][lane] = cur[3];
             sh4[par][row][lane] = cur[4];
-            load_at(z + D, ring[u]);
+            if (refill) load_at(z + D, ring[u]);
             float nxt[7], hnxt;
             collide_at(ring[(u + 1) % D], nxt, hnxt);  // plane z + 1
             lds_barrier();
@@ -451,7 +459,16 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
 #pragma unroll
             for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
             hcur = hnxt;
-        }
+    };
+    // planes z0 - 1 .. z1 are needed; only the last block has refills to skip
+    int zb = z0;
+    for (; zb + 2 * D - 1 <= z1; zb += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) plane_step(u, zb + u, true);
+    }
+    for (; zb < z1; zb += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) plane_step(u, zb + u, zb + u + D <= z1);
     }
 }
 
@@ -585,9 +602,11 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         const int strips = (nx + kStrip - 1) / kStrip;
         // Rows per wavefront: short marches leave more wavefronts to share the
         // chip, long ones amortise the two halo rows.  Measured best on MI355X:
-        // 8 rows up to 512 rows of grid, 16 beyond (1024^2 and 4096^2).
+        // 16 rows for 1024^2 (one wavefront per SIMD), 8 for small grids and
+        // for grids of 8 M nodes and more (4096^2), where the extra
+        // wavefronts hide more HBM latency than the halo rows cost.
         int rows = collide_rows_override();
-        if (rows <= 0) rows = ny <= 512 ? 8 : 16;
+        if (rows <= 0) rows = (ny <= 512 || (int64_t)nx * ny >= ((int64_t)1 << 23)) ? 8 : 16;
         const int chunks = (ny + rows - 1) / rows;
         const int waves = strips * chunks;
         const unsigned blocks = (unsigned)((waves + 3) / 4);
