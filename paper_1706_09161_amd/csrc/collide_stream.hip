@@ -46,6 +46,18 @@ namespace {
 
 constexpr int kStrip = 64;  // output columns per wavefront
 
+// Tile index of workgroup b of nb.  Workgroups are dealt to the 8 XCDs round
+// robin (b mod 8); this gives each XCD one contiguous range of tiles instead,
+// so the halo lines that neighbouring tiles both read (the node columns beside
+// a strip, the rows or planes beside a march) are fetched once into that XCD's
+// L2 rather than once per XCD.  A bijection of [0, nb): the first nb mod 8
+// XCDs take one tile more.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // 1 / (number of unknown populations) of the Dirichlet rule (at most 3)
 __device__ __forceinline__ float inv_count(int nu) { return nu == 1 ? 1.f : (nu == 2 ? 0.5f : 1.f / 3.f); }
 
@@ -196,7 +208,7 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
     const int nx = cc.n[0], ny = cc.n[1];
     const int64_t nodes = (int64_t)nx * ny;
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int gw = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (gw >= total_waves) return;  // whole wavefront exits together
     const int strip = gw % strips, chunk = gw / strips;
     const int x0 = strip * kStrip;
@@ -343,7 +355,7 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
     const int64_t plane = (int64_t)nx * ny;
     const int64_t nodes = plane * nz;
     const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
-    int b = blockIdx.x;
+    int b = xcd_tile(blockIdx.x, gridDim.x);
     const int sx = b % strips_x;
     b /= strips_x;
     const int sy = b % strips_y;
@@ -579,7 +591,8 @@ void with_flags(bool a, bool b, bool c, F&& f)
     }
 }
 
-// Rows per wavefront of the 2D kernel forced by LBM_COLLIDE_ROWS (tuning; 0 = automatic).
+// March length forced by LBM_COLLIDE_ROWS (tuning; 0 = automatic): rows per
+// wavefront of the 2D kernel, planes per workgroup of the 3D kernel.
 int collide_rows_override()
 {
     const char* e = getenv("LBM_COLLIDE_ROWS");
@@ -601,12 +614,12 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         const int nx = cc.n[0], ny = cc.n[1];
         const int strips = (nx + kStrip - 1) / kStrip;
         // Rows per wavefront: short marches leave more wavefronts to share the
-        // chip, long ones amortise the two halo rows.  Measured best on MI355X:
-        // 16 rows for 1024^2 (one wavefront per SIMD), 8 for small grids and
-        // for grids of 8 M nodes and more (4096^2), where the extra
-        // wavefronts hide more HBM latency than the halo rows cost.
+        // chip, long ones amortise the two halo rows (which the neighbouring
+        // march on the same XCD mostly has in L2 already).  Measured on
+        // MI355X: 1024^2 runs 11.2 us with 8 rows, 11.9 with 16, 17.2 with
+        // 32; 4096^2 runs 180 us with 8 rows and 175 with 16 or 32.
         int rows = collide_rows_override();
-        if (rows <= 0) rows = (ny <= 512 || (int64_t)nx * ny >= ((int64_t)1 << 23)) ? 8 : 16;
+        if (rows <= 0) rows = (int64_t)nx * ny >= ((int64_t)1 << 23) ? 16 : 8;
         const int chunks = (ny + rows - 1) / rows;
         const int waves = strips * chunks;
         const unsigned blocks = (unsigned)((waves + 3) / 4);
@@ -622,21 +635,26 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         });
         return hipGetLastError();
     }
-    // NY rows per workgroup: 16 (one wave per row, 4 waves per SIMD, at most
-    // 128 VGPRs); the space-dependent variant holds 9 more values per ring
-    // plane and runs 8 rows (256 VGPRs) rather than spill.
+    // NY = 8 rows per workgroup (one wave per row, 6 output rows): two
+    // workgroups share a CU, and the y-halo rows of one come from L2 lines its
+    // neighbour on the same XCD has fetched.  At 256^3, 313 us against 322
+    // with 16-row workgroups; the space-dependent variant (9 more values per
+    // ring plane, up to 256 VGPRs) also needs the smaller workgroup.
     auto launch3d = [&](auto ny_c, auto hs, auto pk, auto vr) {
         constexpr int NY = decltype(ny_c)::value;
         const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
         const int sx = (nx + kStrip - 1) / kStrip;
         const int sy = (ny + (NY - 2) - 1) / (NY - 2);
-        // Long z marches amortise the two halo planes, but one 16-wave workgroup
-        // fills a CU, and a queue of about 4 workgroups per CU lets a new one
-        // start its ring while the others march: at 256^3, 16-plane marches
-        // (1216 workgroups) run 325 us, 32-plane 343 us, 64-plane 401 us, and
-        // one resident round of 256 equal shares 389 us.
-        int planes = 64;
-        while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 1024) planes /= 2;
+        // Long z marches amortise the two halo planes; a queue of a few
+        // workgroups per CU lets a new one start its ring while the others
+        // march (with 16-row workgroups at 256^3: 16-plane marches 325 us,
+        // 32-plane 343 us, 64-plane 401 us, one resident round of 256 equal
+        // shares 389 us).
+        int planes = collide_rows_override();
+        if (planes <= 0) {
+            planes = 64;
+            while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 1024) planes /= 2;
+        }
         const int chunks = (nz + planes - 1) / planes;
         const int64_t blocks = (int64_t)sx * sy * chunks;
         if (blocks > 0x7fffffff) return hipErrorInvalidValue;
@@ -647,12 +665,8 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         return hipSuccess;
     };
     hipError_t e = hipSuccess;
-    with_flags(S != nullptr, Cp_out != nullptr, var, [&](auto hs, auto pk, auto vr) {
-        if constexpr (decltype(vr)::value)
-            e = launch3d(std::integral_constant<int, 8>{}, hs, pk, vr);
-        else
-            e = launch3d(std::integral_constant<int, 16>{}, hs, pk, vr);
-    });
+    with_flags(S != nullptr, Cp_out != nullptr, var,
+               [&](auto hs, auto pk, auto vr) { e = launch3d(std::integral_constant<int, 8>{}, hs, pk, vr); });
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
