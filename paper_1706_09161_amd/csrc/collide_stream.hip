@@ -110,10 +110,34 @@ __device__ __forceinline__ float flux_delta(const float (&dev)[Q], const float* 
     return s;
 }
 
+// The equilibrium carries the node's mass: sum_i f^eq_i = C = sum_i f_i
+// (equation (Feq)), so the deviations f - f^eq have zero sum and the collision
+// conserves mass.  In FP32 the rounded f^eq_i leave a sum of a few ulp of C,
+// which the mass row of the collision operator turns into a mass change of
+// the same size at every node and step; it does not decay (mass is
+// conserved) and over thousands of steps it is the largest error of the FP32
+// scheme.  Taking the rounded sum off the rest population restores the zero
+// sum up to an ulp of the deviations (exact arithmetic subtracts 0).
+template <int Q>
+__device__ __forceinline__ void remove_mass_defect(float (&dev)[Q])
+{
+#pragma clang fp contract(off)
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) m += dev[i];
+    dev[0] -= m;
+}
+
 template <int Q, bool VAR>
 __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
                                     float S, const float* db, float (&fs)[Q])
 {
+    // Products are fused only where fmaf says so (and fmaf is used wherever a
+    // product meets a sum): every inlined copy of this function (the rows
+    // before a march, the march, its last block) then rounds alike, and a
+    // node's result does not depend on where in a march it falls or on the
+    // march length.
+#pragma clang fp contract(off)
     constexpr int d = (Q - 1) / 2;
     float C = 0.f;
 #pragma unroll
@@ -122,17 +146,17 @@ __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q]
     float sphi = 0.f;
 #pragma unroll
     for (int mu = 0; mu < d; ++mu) sphi += phi[mu];
-    feq[0] = C - cc.w[0] * sphi;
+    feq[0] = fmaf(-cc.w[0], sphi, C);
 #pragma unroll
     for (int mu = 0; mu < d; ++mu) {
         const float a = cc.w[2 * mu + 1] * phi[mu];
-        const float b = cc.adv[mu] * C;
-        feq[2 * mu + 1] = a + b;
-        feq[2 * mu + 2] = a - b;
+        feq[2 * mu + 1] = fmaf(cc.adv[mu], C, a);
+        feq[2 * mu + 2] = fmaf(-cc.adv[mu], C, a);
     }
     float dev[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) dev[i] = f[i] - feq[i];
+    remove_mass_defect<Q>(dev);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         float r = 0.f;
@@ -144,9 +168,9 @@ __device__ inline void collide_node(const CollideConsts& cc, const float (&f)[Q]
     if (VAR) {
 #pragma unroll
         for (int a = 0; a < d; ++a) {
-            const float h = 0.5f * flux_delta<Q>(dev, db, a);
-            fs[2 * a + 1] -= h;
-            fs[2 * a + 2] += h;
+            const float delta = flux_delta<Q>(dev, db, a);
+            fs[2 * a + 1] = fmaf(-0.5f, delta, fs[2 * a + 1]);
+            fs[2 * a + 2] = fmaf(0.5f, delta, fs[2 * a + 2]);
         }
     }
 }
@@ -157,6 +181,8 @@ template <int Q, bool VAR>
 __device__ inline void collide_x_pair(const CollideConsts& cc, const float (&f)[Q], const float (&phi)[(Q - 1) / 2],
                                       float S, const float* db, float& f1, float& f2)
 {
+    // the same operations as collide_node's populations 1 and 2, fused alike
+#pragma clang fp contract(off)
     constexpr int d = (Q - 1) / 2;
     float C = 0.f;
 #pragma unroll
@@ -165,17 +191,17 @@ __device__ inline void collide_x_pair(const CollideConsts& cc, const float (&f)[
     float sphi = 0.f;
 #pragma unroll
     for (int mu = 0; mu < d; ++mu) sphi += phi[mu];
-    feq[0] = C - cc.w[0] * sphi;
+    feq[0] = fmaf(-cc.w[0], sphi, C);
 #pragma unroll
     for (int mu = 0; mu < d; ++mu) {
         const float x = cc.w[2 * mu + 1] * phi[mu];
-        const float y = cc.adv[mu] * C;
-        feq[2 * mu + 1] = x + y;
-        feq[2 * mu + 2] = x - y;
+        feq[2 * mu + 1] = fmaf(cc.adv[mu], C, x);
+        feq[2 * mu + 2] = fmaf(-cc.adv[mu], C, x);
     }
     float dev[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) dev[j] = f[j] - feq[j];
+    remove_mass_defect<Q>(dev);
     float ra = 0.f, rb = 0.f;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -189,8 +215,8 @@ __device__ inline void collide_x_pair(const CollideConsts& cc, const float (&f)[
         float s = 0.f;
 #pragma unroll
         for (int b = 0; b < d; ++b) s = fmaf(db[b], dev[2 * b + 1] - dev[2 * b + 2], s);
-        f1 -= 0.5f * s;
-        f2 += 0.5f * s;
+        f1 = fmaf(-0.5f, s, f1);
+        f2 = fmaf(0.5f, s, f2);
     }
 }
 
@@ -616,10 +642,11 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         // Rows per wavefront: short marches leave more wavefronts to share the
         // chip, long ones amortise the two halo rows (which the neighbouring
         // march on the same XCD mostly has in L2 already).  Measured on
-        // MI355X: 1024^2 runs 11.2 us with 8 rows, 11.9 with 16, 17.2 with
-        // 32; 4096^2 runs 180 us with 8 rows and 175 with 16 or 32.
+        // MI355X (4 / 8 / 16 / 32 rows): 512^2 5.0 / 6.8 / 9.8 / 15.6 us,
+        // 1024^2 11.7 / 11.5 / 11.8 / 17.0, 2048^2 33.6 / 36.3 / 35.5 / 34.9,
+        // 4096^2 182 / 180 / 175 / 175.
         int rows = collide_rows_override();
-        if (rows <= 0) rows = (int64_t)nx * ny >= ((int64_t)1 << 23) ? 16 : 8;
+        if (rows <= 0) rows = (int64_t)nx * ny >= ((int64_t)1 << 23) ? 16 : 4;
         const int chunks = (ny + rows - 1) / rows;
         const int waves = strips * chunks;
         const unsigned blocks = (unsigned)((waves + 3) / 4);
@@ -645,15 +672,15 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
         const int sx = (nx + kStrip - 1) / kStrip;
         const int sy = (ny + (NY - 2) - 1) / (NY - 2);
-        // Long z marches amortise the two halo planes; a queue of a few
+        // Long z marches amortise the two halo planes; a queue of several
         // workgroups per CU lets a new one start its ring while the others
-        // march (with 16-row workgroups at 256^3: 16-plane marches 325 us,
-        // 32-plane 343 us, 64-plane 401 us, one resident round of 256 equal
-        // shares 389 us).
+        // march.  Measured on MI355X (8 / 16 / 32 / 64 planes): 128^3 33 / 38 /
+        // 39 / 69 us, 256^3 319 / 309 / 312 / 318, 384^3 1019 / 975 / 946 / 939:
+        // the longest march that still gives 2048 workgroups.
         int planes = collide_rows_override();
         if (planes <= 0) {
             planes = 64;
-            while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 1024) planes /= 2;
+            while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 2048) planes /= 2;
         }
         const int chunks = (nz + planes - 1) / planes;
         const int64_t blocks = (int64_t)sx * sy * chunks;
