@@ -182,6 +182,8 @@ def adjoint_ratio(torch, LbmFade, synth):
         s.set_C(C0)
         s.adjoint(steps, K, gC)  # warm-up (allocates checkpoints)
         s.set_C(C0)
+        s.step(steps)  # warm-up (captures the step graph)
+        s.set_C(C0)
         torch.cuda.synchronize()
         t = time.perf_counter()
         s.step(steps)

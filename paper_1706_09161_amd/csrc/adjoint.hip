@@ -9,10 +9,15 @@
 //       fbar^eq = R^T fbar*,  fbar += fbar* - R^T fbar*,  dL/dS += dt <w, fbar*>,
 //       dL/dR += fbar* (f^eq - f)^T;
 //   equilibrium (Feq), (CoeffA) reversed: Cbar, Phibar_mu, dL/du_mu;
-//   fractional term reversed: Cbar += K_mu^T Phibar_mu (transposed Toeplitz GEMM),
-//       dL/dp_mu += <Phibar_mu, (dK_mu/dp_mu) C> (one more Toeplitz GEMM);
+//   fractional term reversed: with K_mu = s (p W+ + (1 - p) W-) + boundary
+//       columns (W+ the lower, W- the upper Toeplitz sums of the weights, unit
+//       diagonal), the two triangular products U = s W+^T Phibar_mu and
+//       L = s W-^T Phibar_mu (one GEMM's worth of MFMA work for the pair) give
+//       Cbar += K_mu^T Phibar_mu = p U + (1 - p) L and
+//       dL/dp_mu += <Phibar_mu, (dK_mu/dp_mu) C> = <U - L, C> + the boundary
+//       columns' p-derivatives against C at the line's two walls;
 //   moment reversed: fbar_i += Cbar.
-// The transposed operator omits the two boundary ROWS of K^T: they only add to
+// The transposed products omit the two boundary ROWS of K^T: they only add to
 // Cbar at wall nodes, whose broadcast into fbar is cancelled exactly by the
 // reversed Dirichlet rule (and by the reversed initial equilibrium, whose
 // weights satisfy w0 = 2 w), so no gradient depends on them.
@@ -46,21 +51,6 @@ struct AdjConsts {
     float R[kMaxQ * kMaxQ];  // collision matrix, row-major
     float wdt[kMaxQ];        // w_i dt
 };
-
-__device__ inline void coords(const AdjConsts& a, int64_t x, int c[3])
-{
-    c[0] = (int)(x % a.n[0]);
-    const int64_t r = x / a.n[0];
-    c[1] = (int)(r % a.n[1]);
-    c[2] = (int)(r / a.n[1]);
-}
-
-__device__ inline bool on_wall(const AdjConsts& a, const int c[3])
-{
-    bool w = false;
-    for (int mu = 0; mu < a.dim; ++mu) w = w || c[mu] == 0 || c[mu] == a.n[mu] - 1;
-    return w;
-}
 
 // Sum `v` over the workgroup in FP64 (fixed order) into out[0..NV): stored, or
 // (ACC) added to what the slot holds (the workgroup's running sum over steps).
@@ -243,19 +233,6 @@ __global__ __launch_bounds__(kBlock) void adjoint_init_node(AdjConsts ac, const 
     block_sum_store<d>(red, part + (int64_t)blockIdx.x * d);
 }
 
-// sum_x Phibar_mu(x) Psi_mu(x) per axis, FP64 partial sums per workgroup
-template <int D>
-__global__ __launch_bounds__(kBlock) void dot_axes(const float* __restrict__ a, const float* __restrict__ b,
-                                                   double* __restrict__ part, int64_t nodes)
-{
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double red[D];
-#pragma unroll
-    for (int mu = 0; mu < D; ++mu)
-        red[mu] = x < nodes ? (double)a[mu * nodes + x] * (double)b[mu * nodes + x] : 0.0;
-    block_sum_store<D>(red, part + (int64_t)blockIdx.x * D);
-}
-
 // acc[off + v] += sum over workgroups b of part[b * nv + v], fixed order
 __global__ __launch_bounds__(kBlock) void reduce_partials(const double* __restrict__ part, int64_t nblocks, int nv,
                                                           double* __restrict__ acc, int off)
@@ -273,12 +250,51 @@ __global__ __launch_bounds__(kBlock) void reduce_partials(const double* __restri
     if (threadIdx.x == 0) acc[off + v] += sh[0];
 }
 
-// fbar_i = fdir_i + Cbar + sum_mu (K_mu^T Phibar_mu), and per-workgroup FP64
-// partial sums of <Phibar_mu, (dK_mu/dp_mu) C> (psi = (dK/dp) C)
+// The reversed fractional term of every axis at node x: returns
+// sum_mu K_mu^T Phibar_mu = sum_mu (p U + (1 - p) L), and sets red[mu] to the
+// node's part of <Phibar_mu, (dK_mu/dp) C>: (U - L)(x) C(x) plus
+// Phibar_mu(x) (dc0_j C(x_0) + dcN_j C(x_N)), j = x's index along the line
+// and x_0, x_N the line's wall nodes (the p-derivatives of the boundary
+// columns).
+struct RevConsts {
+    int n[3];
+    int64_t stride[3];
+    float p[3];
+    const float* dc0[3];
+    const float* dcN[3];
+};
+
 template <int D>
-__global__ __launch_bounds__(kBlock) void combine_dot(const float* __restrict__ fdir, const float* __restrict__ cbar,
-                                                      const float* __restrict__ kt, const float* __restrict__ phibar,
-                                                      const float* __restrict__ psi, float* __restrict__ fbar, int Q,
+__device__ inline float reversed_fractional(const RevConsts& rc, const float* __restrict__ tu,
+                                            const float* __restrict__ tl, const float* __restrict__ phibar,
+                                            const float* __restrict__ C, int64_t x, int64_t nodes, double (&red)[D])
+{
+    int c[3];
+    c[0] = (int)(x % rc.n[0]);
+    const int64_t r = x / rc.n[0];
+    c[1] = (int)(r % rc.n[1]);
+    c[2] = (int)(r / rc.n[1]);
+    const double Cx = (double)C[x];
+    float kt = 0.f;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const float u = tu[mu * nodes + x], l = tl[mu * nodes + x];
+        kt += fmaf(rc.p[mu], u - l, l);
+        const int j = c[mu], N = rc.n[mu] - 1;
+        const double walls = (double)rc.dc0[mu][j] * (double)C[x - (int64_t)j * rc.stride[mu]] +
+                             (double)rc.dcN[mu][j] * (double)C[x + (int64_t)(N - j) * rc.stride[mu]];
+        red[mu] = ((double)u - (double)l) * Cx + (double)phibar[mu * nodes + x] * walls;
+    }
+    return kt;
+}
+
+// fbar_i = fdir_i + Cbar + sum_mu K_mu^T Phibar_mu, and the per-workgroup FP64
+// running sums of <Phibar_mu, (dK_mu/dp_mu) C>
+template <int D>
+__global__ __launch_bounds__(kBlock) void combine_dot(RevConsts rc, const float* __restrict__ fdir,
+                                                      const float* __restrict__ cbar, const float* __restrict__ tu,
+                                                      const float* __restrict__ tl, const float* __restrict__ phibar,
+                                                      const float* __restrict__ C, float* __restrict__ fbar, int Q,
                                                       double* __restrict__ part, int64_t nodes)
 {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -286,39 +302,41 @@ __global__ __launch_bounds__(kBlock) void combine_dot(const float* __restrict__ 
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) red[mu] = 0.0;
     if (x < nodes) {
-        float c = cbar[x];
-#pragma unroll
-        for (int mu = 0; mu < D; ++mu) {
-            c += kt[mu * nodes + x];
-            red[mu] = (double)phibar[mu * nodes + x] * (double)psi[mu * nodes + x];
-        }
+        const float c = cbar[x] + reversed_fractional<D>(rc, tu, tl, phibar, C, x, nodes, red);
         for (int i = 0; i < Q; ++i) fbar[i * nodes + x] = fdir[i * nodes + x] + c;
     }
     block_sum_store<D, true>(red, part + (int64_t)blockIdx.x * D);  // running sum over the reverse sweep
 }
 
-// fbar_i = fdir_i + Cbar + sum_mu (K_mu^T Phibar_mu)
-__global__ void combine_kernel(const float* __restrict__ fdir, const float* __restrict__ cbar,
-                               const float* __restrict__ kt, float* __restrict__ fbar, int Q, int d, int64_t nodes)
-{
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nodes) return;
-    float c = cbar[x];
-    for (int mu = 0; mu < d; ++mu) c += kt[mu * nodes + x];
-    for (int i = 0; i < Q; ++i) fbar[i * nodes + x] = fdir[i * nodes + x] + c;
-}
-
+// Reversed fractional term of the initial equilibrium: per-workgroup FP64
+// sums of <Phibar_mu, (dK_mu/dp_mu) C0'>, and (when dC0 is given)
 // dC0 = Cbar + sum_mu K_mu^T Phibar_mu, zero on the (overwritten) wall nodes
-__global__ void final_dC0(AdjConsts ac, const float* __restrict__ cbar, const float* __restrict__ kt,
-                          float* __restrict__ dC0, int64_t nodes)
+template <int D>
+__global__ __launch_bounds__(kBlock) void combine_init(RevConsts rc, const float* __restrict__ cbar,
+                                                       const float* __restrict__ tu, const float* __restrict__ tl,
+                                                       const float* __restrict__ phibar, const float* __restrict__ C,
+                                                       float* __restrict__ dC0, double* __restrict__ part,
+                                                       int64_t nodes)
 {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nodes) return;
-    int c[3];
-    coords(ac, x, c);
-    float v = cbar[x];
-    for (int mu = 0; mu < ac.dim; ++mu) v += kt[mu * nodes + x];
-    dC0[x] = on_wall(ac, c) ? 0.f : v;
+    double red[D];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) red[mu] = 0.0;
+    if (x < nodes) {
+        const float v = cbar[x] + reversed_fractional<D>(rc, tu, tl, phibar, C, x, nodes, red);
+        if (dC0) {
+            bool wall = false;
+            int64_t r = x;
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) {
+                const int c = (int)(r % rc.n[mu]);
+                r /= rc.n[mu];
+                wall = wall || c == 0 || c == rc.n[mu] - 1;
+            }
+            dC0[x] = wall ? 0.f : v;
+        }
+    }
+    block_sum_store<D>(red, part + (int64_t)blockIdx.x * D);
 }
 
 unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -330,36 +348,49 @@ struct AdjointState {
     int K = 0;           // checkpoint interval the buffers were sized for
     int64_t nseg = 0;    // checkpoints allocated
     float* ckpt = nullptr;
-    float* seg_f = nullptr;    // (K+1) slots of Q * nodes; slot 0 unused (the checkpoint is read directly)
-    float* seg_phi = nullptr;  // K slots of d * nodes
-    float* seg_C = nullptr;    // K slots of nodes
+    // recomputed segments, double-buffered (nbuf = 2) when both fit, so that
+    // the next segment's recompute runs on a side stream during this
+    // segment's reverse sweep
+    int nbuf = 0;
+    float* seg_f[2] = {nullptr, nullptr};    // (K+1) slots of Q * nodes; slot 0 unused (the checkpoint is read directly)
+    float* seg_phi[2] = {nullptr, nullptr};  // K slots of d * nodes
+    float* seg_C[2] = {nullptr, nullptr};    // K slots of nodes
+    hipStream_t side = nullptr;              // default priority, non-blocking
+    hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
     float* fbar = nullptr;
     float* fdir = nullptr;
     float* cbar = nullptr;
     float* phibar = nullptr;
-    float* kt = nullptr;
-    float* psi = nullptr;
+    float* tu = nullptr;  // s W+^T Phibar_mu (d fields)
+    float* tl = nullptr;  // s W-^T Phibar_mu (d fields)
     float* dS = nullptr;
     double* part = nullptr;   // per-workgroup partial sums of adjoint_node
     double* part2 = nullptr;  // per-workgroup partial sums of the p-gradient
     double* acc = nullptr;
     void* opmem = nullptr;
-    AxisOp opsT[3], opsP[3];
+    AxisOp opsU[3], opsL[3];
+    RevConsts rc;
 };
 
 void adjoint_free(AdjointState* a)
 {
     if (!a) return;
-    void* ptrs[] = {a->ckpt, a->seg_f, a->seg_phi, a->seg_C, a->fbar, a->fdir, a->cbar,
-                    a->phibar, a->kt, a->psi, a->dS, a->part, a->part2, a->acc, a->opmem};
+    void* ptrs[] = {a->ckpt, a->seg_f[0], a->seg_phi[0], a->seg_C[0], a->seg_f[1], a->seg_phi[1], a->seg_C[1],
+                    a->fbar, a->fdir, a->cbar, a->phibar, a->tu, a->tl, a->dS, a->part, a->part2, a->acc, a->opmem};
     for (void* p : ptrs) (void)hipFree(p);
+    hipEvent_t evs[] = {a->ev_fwd, a->ev_rec[0], a->ev_rec[1], a->ev_rev[0], a->ev_rev[1]};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    if (a->side) (void)hipStreamDestroy(a->side);
     delete a;
 }
 
 namespace {
 
-// Build the transposed operator (generator T(-d), no boundary columns) and the
-// p-derivative operator dK/dp = s (W+ - W-) of every axis (FP32).
+// Build, per axis, the two triangular products of the reversed fractional
+// term (generators of s W+^T and s W-^T, no boundary columns) and the
+// p-derivatives of the forward operator's two boundary columns (FP64, then
+// FP32).
 bool build_ops(lbm_fade* h, AdjointState* A)
 {
     const int d = h->dim;
@@ -367,7 +398,7 @@ bool build_ops(lbm_fade* h, AdjointState* A)
     size_t bytes = 0;
     for (int mu = 0; mu < d; ++mu) {
         const size_t n = (size_t)h->grid.n[mu];
-        bytes += 2 * r256(sizeof(float) * (2 * n - 1)) + 4 * r256(sizeof(float) * n);
+        bytes += 2 * r256(sizeof(float) * (2 * n - 1)) + 3 * r256(sizeof(float) * n);
     }
     std::vector<unsigned char> host(bytes, 0);
     if (hipMalloc(&A->opmem, bytes) != hipSuccess) return false;
@@ -378,33 +409,31 @@ bool build_ops(lbm_fade* h, AdjointState* A)
         return o;
     };
     unsigned char* base = reinterpret_cast<unsigned char*>(A->opmem);
+    RevConsts& rc = A->rc;
+    memset(&rc, 0, sizeof(rc));
+    for (int mu = 0; mu < 3; ++mu) rc.n[mu] = h->cc.n[mu];
+    rc.stride[0] = 1;
+    rc.stride[1] = h->cc.n[0];
+    rc.stride[2] = (int64_t)h->cc.n[0] * h->cc.n[1];
     for (int mu = 0; mu < d; ++mu) {
         const int n = h->grid.n[mu], N = n - 1;
-        const double p = h->params.p[mu];
         const AxisCoeffs C = axis_coeffs(n, 2.0 - h->params.alpha[mu], h->params.g[mu], h->grid.dx);
         const double s = C.s;
-        const size_t oT = carve(sizeof(float) * (2 * n - 1)), oP = carve(sizeof(float) * (2 * n - 1));
-        const size_t oT0 = carve(sizeof(float) * n), oTN = carve(sizeof(float) * n);
-        const size_t oP0 = carve(sizeof(float) * n), oPN = carve(sizeof(float) * n);
-        float* gT = reinterpret_cast<float*>(host.data() + oT);
-        float* gP = reinterpret_cast<float*>(host.data() + oP);
-        float* pc0 = reinterpret_cast<float*>(host.data() + oP0);
-        float* pcN = reinterpret_cast<float*>(host.data() + oPN);
+        const size_t oU = carve(sizeof(float) * (2 * n - 1)), oL = carve(sizeof(float) * (2 * n - 1));
+        const size_t oZ = carve(sizeof(float) * n);
+        const size_t o0 = carve(sizeof(float) * n), oN = carve(sizeof(float) * n);
+        float* gU = reinterpret_cast<float*>(host.data() + oU);
+        float* gL = reinterpret_cast<float*>(host.data() + oL);
+        float* pc0 = reinterpret_cast<float*>(host.data() + o0);
+        float* pcN = reinterpret_cast<float*>(host.data() + oN);
+        // generator index dd = j - k (output j, input k): W+ holds a_{j-k} for
+        // j >= k, so s W+^T holds s a_{k-j} for j <= k (upper); W- holds
+        // a_{k-j} for j <= k, so s W-^T holds s a_{j-k} for j >= k (lower)
         for (int dd = -N; dd <= N; ++dd) {
-            // forward T(dd) and its transpose T^T(dd) = T(-dd)
-            const int e = -dd;
-            double tT;
-            if (e > 0) tT = s * p * C.a[e];
-            else if (e < 0) tT = s * (1.0 - p) * C.a[-e];
-            else tT = s * (p * 1.0 + (1.0 - p) * 1.0);
-            gT[dd + N] = (float)tT;
-            double tP;
-            if (dd > 0) tP = s * C.a[dd];
-            else if (dd < 0) tP = -s * C.a[-dd];
-            else tP = 0.0;
-            gP[dd + N] = (float)tP;
+            gU[dd + N] = dd <= 0 ? (float)(s * C.a[-dd]) : 0.f;
+            gL[dd + N] = dd >= 0 ? (float)(s * C.a[dd]) : 0.f;
         }
-        // d(corr0)/dp and d(corrN)/dp of the forward operator (make_axis_weights), FP64
+        // d(corr0)/dp and d(corrN)/dp of the forward operator (make_axis_weights)
         {
             const double gm = 2.0 - h->params.alpha[mu];
             const double empty = pow(0.0, gm);  // c+_{00} = c-_{NN}
@@ -424,23 +453,23 @@ bool build_ops(lbm_fade* h, AdjointState* A)
                 pcN[j] = (float)dN[j];
             }
         }
-        AxisOp& T = A->opsT[mu];
-        T.n = n;
-        T.lower_only = h->ops[mu].upper_only;
-        T.upper_only = h->ops[mu].lower_only;
-        T.gen = reinterpret_cast<const float*>(base + oT);
-        T.corr0 = reinterpret_cast<const float*>(base + oT0);  // zeros
-        T.corrN = reinterpret_cast<const float*>(base + oTN);  // zeros
-        T.gen_hi = T.gen_lo = nullptr;
-        T.pw_hi = T.pw_lo = nullptr;
-        AxisOp& P = A->opsP[mu];
-        P.n = n;
-        P.lower_only = P.upper_only = 0;
-        P.gen = reinterpret_cast<const float*>(base + oP);
-        P.corr0 = reinterpret_cast<const float*>(base + oP0);
-        P.corrN = reinterpret_cast<const float*>(base + oPN);
-        P.gen_hi = P.gen_lo = nullptr;
-        P.pw_hi = P.pw_lo = nullptr;
+        const float* zeros = reinterpret_cast<const float*>(base + oZ);
+        AxisOp& U = A->opsU[mu];
+        U.n = n;
+        U.lower_only = 0;
+        U.upper_only = 1;
+        U.gen = reinterpret_cast<const float*>(base + oU);
+        U.corr0 = U.corrN = zeros;
+        U.gen_hi = U.gen_lo = nullptr;
+        U.pw_hi = U.pw_lo = nullptr;
+        AxisOp& L = A->opsL[mu];
+        L = U;
+        L.lower_only = 1;
+        L.upper_only = 0;
+        L.gen = reinterpret_cast<const float*>(base + oL);
+        rc.p[mu] = (float)h->params.p[mu];
+        rc.dc0[mu] = reinterpret_cast<const float*>(base + o0);
+        rc.dcN[mu] = reinterpret_cast<const float*>(base + oN);
     }
     return hipMemcpy(A->opmem, host.data(), bytes, hipMemcpyHostToDevice) == hipSuccess;
 }
@@ -458,23 +487,44 @@ bool alloc_state(lbm_fade* h, AdjointState* A, int64_t n, int K)
     const int Q = h->Q, d = h->dim;
     const int64_t nseg = (n + K - 1) / K > 0 ? (n + K - 1) / K : 1;
     if (A->ckpt && A->K == K && A->nseg >= nseg) return true;
-    void* old[] = {A->ckpt, A->seg_f, A->seg_phi, A->seg_C};
+    void* old[] = {A->ckpt, A->seg_f[0], A->seg_phi[0], A->seg_C[0], A->seg_f[1], A->seg_phi[1], A->seg_C[1]};
     for (void* p : old) (void)hipFree(p);
-    A->ckpt = A->seg_f = A->seg_phi = A->seg_C = nullptr;
+    A->ckpt = nullptr;
+    for (int b = 0; b < 2; ++b) A->seg_f[b] = A->seg_phi[b] = A->seg_C[b] = nullptr;
+    A->nbuf = 0;
     A->K = K;
     A->nseg = nseg;
     const size_t fq = sizeof(float) * Q * nodes;
     if (hipMalloc(&A->ckpt, fq * nseg) != hipSuccess) return false;
-    if (hipMalloc(&A->seg_f, fq * (K + 1)) != hipSuccess) return false;
-    if (hipMalloc(&A->seg_phi, sizeof(float) * d * nodes * K) != hipSuccess) return false;
-    if (hipMalloc(&A->seg_C, sizeof(float) * nodes * K) != hipSuccess) return false;
+    for (int b = 0; b < 2; ++b) {
+        const bool ok = hipMalloc(&A->seg_f[b], fq * (K + 1)) == hipSuccess &&
+                        hipMalloc(&A->seg_phi[b], sizeof(float) * d * nodes * K) == hipSuccess &&
+                        hipMalloc(&A->seg_C[b], sizeof(float) * nodes * K) == hipSuccess;
+        if (!ok) {
+            // a second buffer is an optimisation: run single-buffered without it
+            (void)hipGetLastError();
+            (void)hipFree(A->seg_f[b]);
+            (void)hipFree(A->seg_phi[b]);
+            (void)hipFree(A->seg_C[b]);
+            A->seg_f[b] = A->seg_phi[b] = A->seg_C[b] = nullptr;
+            if (b == 0) return false;
+            break;
+        }
+        A->nbuf = b + 1;
+    }
+    if (!A->side) {
+        if (hipStreamCreateWithFlags(&A->side, hipStreamNonBlocking) != hipSuccess) return false;
+        hipEvent_t* evs[] = {&A->ev_fwd, &A->ev_rec[0], &A->ev_rec[1], &A->ev_rev[0], &A->ev_rev[1]};
+        for (hipEvent_t* e : evs)
+            if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return false;
+    }
     if (!A->fbar) {
         const int64_t nb = (nodes + kBlock - 1) / kBlock;
         if (hipMalloc(&A->fbar, fq) != hipSuccess || hipMalloc(&A->fdir, fq) != hipSuccess ||
             hipMalloc(&A->cbar, sizeof(float) * nodes) != hipSuccess ||
             hipMalloc(&A->phibar, sizeof(float) * d * nodes) != hipSuccess ||
-            hipMalloc(&A->kt, sizeof(float) * d * nodes) != hipSuccess ||
-            hipMalloc(&A->psi, sizeof(float) * d * nodes) != hipSuccess ||
+            hipMalloc(&A->tu, sizeof(float) * d * nodes) != hipSuccess ||
+            hipMalloc(&A->tl, sizeof(float) * d * nodes) != hipSuccess ||
             hipMalloc(&A->dS, sizeof(float) * nodes) != hipSuccess ||
             hipMalloc(&A->part, sizeof(double) * nb_node_max(h) * (3 * 3 + 3 + 1)) != hipSuccess ||
             hipMalloc(&A->part2, sizeof(double) * nb * 3) != hipSuccess ||
@@ -535,23 +585,22 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     const int NV = d * d + d + 1;  // flux block of dL/dLambda, dL/du, tr dL/dR
     const dim3 node_grid((unsigned)((ac.n[0] + kBlock - 1) / kBlock), (unsigned)ac.n[1], (unsigned)(d == 3 ? ac.n[2] : 1));
     const int64_t nb_node = (int64_t)node_grid.x * node_grid.y * node_grid.z;
-    // the two operators of the reversed fractional term of every axis, one launch:
-    // K^T Phibar (into kt) and (dK/dp) C (into psi)
+    // the two triangular products of the reversed fractional term of every
+    // axis, one launch: s W+^T Phibar (into tu) and s W-^T Phibar (into tl)
     AxisOp ops2[2 * 3];
     AxisLayout lays2[2 * 3];
     for (int mu = 0; mu < d; ++mu) {
-        ops2[mu] = A->opsT[mu];
-        ops2[d + mu] = A->opsP[mu];
+        ops2[mu] = A->opsU[mu];
+        ops2[d + mu] = A->opsL[mu];
         lays2[mu] = lays2[d + mu] = h->lays[mu];
     }
-    auto reversed_phi = [&](const float* Cin) -> hipError_t {
+    auto reversed_phi = [&]() -> hipError_t {
         const float* in[2 * 3];
         float* outp[2 * 3];
         for (int mu = 0; mu < d; ++mu) {
-            in[mu] = A->phibar + (int64_t)mu * nodes;
-            outp[mu] = A->kt + (int64_t)mu * nodes;
-            in[d + mu] = Cin;
-            outp[d + mu] = A->psi + (int64_t)mu * nodes;
+            in[mu] = in[d + mu] = A->phibar + (int64_t)mu * nodes;
+            outp[mu] = A->tu + (int64_t)mu * nodes;
+            outp[d + mu] = A->tl + (int64_t)mu * nodes;
         }
         return launch_fractional_ops(ops2, lays2, in, outp, 2 * d, s);
     };
@@ -584,42 +633,79 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     hipLaunchKernelGGL(broadcast_kernel, dim3(nblk(nodes)), dim3(kBlock), 0, s, gC, A->fbar, Q, nodes);
     ADJ_TRY(hipGetLastError());
     const int offU = d * d, offTr = d * d + d, offP = d * d + d + 1;
-    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
-        const int64_t t0 = sg * K;
-        const int len = (int)((t0 + K <= n ? t0 + K : n) - t0);
-        const float* fck = A->ckpt + sg * Q * nodes;
-        auto f_at = [&](int j) -> const float* { return j == 0 ? fck : A->seg_f + (int64_t)j * Q * nodes; };
-        ADJ_TRY(launch_moment(h->cc, fck, A->seg_C, s));
+    // Segment sg recomputed into buffer b from its checkpoint: populations, C
+    // and Phi of each of its steps.
+    auto seg_len = [&](int64_t sg) { return (int)((sg * K + K <= n ? sg * K + K : n) - sg * K); };
+    auto f_of = [&](int64_t sg, int b, int j) -> const float* {
+        return j == 0 ? A->ckpt + sg * Q * nodes : A->seg_f[b] + (int64_t)j * Q * nodes;
+    };
+    auto recompute = [&](int64_t sg, int b, hipStream_t st) -> int {
+        const int len = seg_len(sg);
+        ADJ_TRY(launch_moment(h->cc, f_of(sg, b, 0), A->seg_C[b], st));
         for (int j = 0; j < len; ++j) {
-            float* phi_j = A->seg_phi + (int64_t)j * d * nodes;
-            int rc = fade_run_phi(h, A->seg_C + (int64_t)j * nodes, phi_j, s);
+            float* phi_j = A->seg_phi[b] + (int64_t)j * d * nodes;
+            int rc = fade_run_phi(h, A->seg_C[b] + (int64_t)j * nodes, phi_j, st);
             if (rc) {
                 msg = "recompute fractional term failed";
                 return rc;
             }
             if (j + 1 < len)
-                ADJ_TRY(launch_collide_stream(h->cc, f_at(j), A->seg_f + (int64_t)(j + 1) * Q * nodes, phi_j, h->S,
-                                              A->seg_C + (int64_t)(j + 1) * nodes, nullptr, s));
+                ADJ_TRY(launch_collide_stream(h->cc, f_of(sg, b, j), A->seg_f[b] + (int64_t)(j + 1) * Q * nodes,
+                                              phi_j, h->S, A->seg_C[b] + (int64_t)(j + 1) * nodes, nullptr, st));
+        }
+        return LBM_OK;
+    };
+    // Double-buffered: the recompute of segment sg - 1 runs on the side stream
+    // while segment sg is swept on s; events order each buffer's reuse.
+    const bool overlap = A->nbuf == 2 && nseg > 1;
+    if (overlap) {
+        ADJ_TRY(hipEventRecord(A->ev_fwd, s));
+        ADJ_TRY(hipStreamWaitEvent(A->side, A->ev_fwd, 0));
+        int rc = recompute(nseg - 1, (int)((nseg - 1) % 2), A->side);
+        if (rc) return rc;
+        ADJ_TRY(hipEventRecord(A->ev_rec[(nseg - 1) % 2], A->side));
+    }
+    bool swept[2] = {false, false};
+    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+        const int len = seg_len(sg);
+        const int b = overlap ? (int)(sg % 2) : 0;
+        if (overlap) {
+            ADJ_TRY(hipStreamWaitEvent(s, A->ev_rec[b], 0));
+            if (sg >= 1) {
+                const int nb2 = 1 - b;
+                if (swept[nb2]) ADJ_TRY(hipStreamWaitEvent(A->side, A->ev_rev[nb2], 0));
+                int rc = recompute(sg - 1, nb2, A->side);
+                if (rc) return rc;
+                ADJ_TRY(hipEventRecord(A->ev_rec[nb2], A->side));
+            }
+        } else {
+            int rc = recompute(sg, 0, s);
+            if (rc) return rc;
         }
         for (int j = len - 1; j >= 0; --j) {
-            const float* phi_j = A->seg_phi + (int64_t)j * d * nodes;
-            const float* C_j = A->seg_C + (int64_t)j * nodes;
+            const float* phi_j = A->seg_phi[b] + (int64_t)j * d * nodes;
+            const float* C_j = A->seg_C[b] + (int64_t)j * nodes;
             if (Q == 5)
-                hipLaunchKernelGGL(adjoint_node<5>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_at(j), phi_j, A->fdir,
-                                   A->cbar, A->phibar, A->dS, A->part, nodes);
+                hipLaunchKernelGGL(adjoint_node<5>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_of(sg, b, j), phi_j,
+                                   A->fdir, A->cbar, A->phibar, A->dS, A->part, nodes);
             else
-                hipLaunchKernelGGL(adjoint_node<7>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_at(j), phi_j, A->fdir,
-                                   A->cbar, A->phibar, A->dS, A->part, nodes);
+                hipLaunchKernelGGL(adjoint_node<7>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_of(sg, b, j), phi_j,
+                                   A->fdir, A->cbar, A->phibar, A->dS, A->part, nodes);
             ADJ_TRY(hipGetLastError());
-            // fractional term reversed: K^T Phibar, and (dK/dp) C for <Phibar, dK/dp C>
-            ADJ_TRY(reversed_phi(C_j));
+            // fractional term reversed: K^T Phibar and <Phibar, (dK/dp) C> from
+            // the two triangular products of Phibar
+            ADJ_TRY(reversed_phi());
             if (d == 2)
-                hipLaunchKernelGGL(combine_dot<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->fdir, A->cbar, A->kt,
-                                   A->phibar, A->psi, A->fbar, Q, A->part2, nodes);
+                hipLaunchKernelGGL(combine_dot<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, A->fdir, A->cbar,
+                                   A->tu, A->tl, A->phibar, C_j, A->fbar, Q, A->part2, nodes);
             else
-                hipLaunchKernelGGL(combine_dot<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->fdir, A->cbar, A->kt,
-                                   A->phibar, A->psi, A->fbar, Q, A->part2, nodes);
+                hipLaunchKernelGGL(combine_dot<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, A->fdir, A->cbar,
+                                   A->tu, A->tl, A->phibar, C_j, A->fbar, Q, A->part2, nodes);
             ADJ_TRY(hipGetLastError());
+        }
+        if (overlap) {
+            ADJ_TRY(hipEventRecord(A->ev_rev[b], s));
+            swept[b] = true;
         }
     }
     hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb_node, NV, A->acc, 0);
@@ -627,7 +713,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part2, nb, d, A->acc, offP);
     ADJ_TRY(hipGetLastError());
     // --- reverse of the initial equilibrium (C0' = C of the initial state)
-    float* C0p = A->seg_C;  // segment 0 left C^0 in slot 0 (or compute it when n == 0)
+    float* C0p = A->seg_C[0];  // segment 0 (buffer 0) left C^0 in slot 0 (or compute it when n == 0)
     if (n == 0) ADJ_TRY(launch_moment(h->cc, A->ckpt, C0p, s));
     if (Q == 5)
         hipLaunchKernelGGL(adjoint_init_node<5>, dim3(nblk(nodes)), dim3(kBlock), 0, s, ac, A->fbar, C0p, A->cbar,
@@ -638,19 +724,18 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     ADJ_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part, nb, d, A->acc, offU);
     ADJ_TRY(hipGetLastError());
-    ADJ_TRY(reversed_phi(C0p));
-    if (d == 2) hipLaunchKernelGGL(dot_axes<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
-    else hipLaunchKernelGGL(dot_axes<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->phibar, A->psi, A->part, nodes);
+    ADJ_TRY(reversed_phi());
+    float* dC0dst = dC0 ? (on_device ? dC0 : A->fdir) : nullptr;  // fdir: scratch for a host destination
+    if (d == 2)
+        hipLaunchKernelGGL(combine_init<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, A->cbar, A->tu, A->tl,
+                           A->phibar, C0p, dC0dst, A->part, nodes);
+    else
+        hipLaunchKernelGGL(combine_init<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, A->cbar, A->tu, A->tl,
+                           A->phibar, C0p, dC0dst, A->part, nodes);
     ADJ_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part, nb, d, A->acc, offP);
     ADJ_TRY(hipGetLastError());
-    if (dC0) {
-        float* dst = dC0;
-        if (!on_device) dst = A->fdir;  // scratch
-        hipLaunchKernelGGL(final_dC0, dim3(nblk(nodes)), dim3(kBlock), 0, s, ac, A->cbar, A->kt, dst, nodes);
-        ADJ_TRY(hipGetLastError());
-        if (!on_device) ADJ_TRY(hipMemcpyAsync(dC0, dst, sizeof(float) * nodes, hipMemcpyDeviceToHost, s));
-    }
+    if (dC0 && !on_device) ADJ_TRY(hipMemcpyAsync(dC0, dC0dst, sizeof(float) * nodes, hipMemcpyDeviceToHost, s));
     if (dS) ADJ_TRY(hipMemcpyAsync(dS, A->dS, sizeof(float) * nodes,
                                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     double acc[64];
