@@ -195,9 +195,13 @@ typedef struct {
  * otherwise).  gC, dC0 and dS are host or device (same on_device), nodes
  * floats each.  The forward states are checkpointed every ckpt_every steps
  * and recomputed per segment; the GEMMs of the reverse sweep run in FP32
- * whatever the handle's precision.  The solver state after the call is the
- * state after n steps.  Synchronises `stream` (the scalar gradients are
- * written to host memory). */
+ * whatever the handle's precision.  Device memory held by the handle after
+ * the first call: ceil(n / ckpt_every) checkpoints of the populations, and two
+ * segment buffers of ckpt_every steps (populations, C and the fractional
+ * terms) when both fit (one otherwise: the recompute then no longer overlaps
+ * the reverse sweep on the handle's internal second stream).  The solver state
+ * after the call is the state after n steps.  Synchronises `stream` (the
+ * scalar gradients are written to host memory). */
 LBM_API int lbm_fade_adjoint(lbm_fade_t h, int64_t n, int32_t ckpt_every, const float* gC, int32_t on_device,
                      lbm_grads* out, float* dC0, float* dS, void* stream);
 
