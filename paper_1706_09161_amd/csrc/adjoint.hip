@@ -29,6 +29,7 @@
 // the chain R -> Lambda -> lambda-bar -> D is applied on the host in FP64.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -657,7 +658,8 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     };
     // Double-buffered: the recompute of segment sg - 1 runs on the side stream
     // while segment sg is swept on s; events order each buffer's reuse.
-    const bool overlap = A->nbuf == 2 && nseg > 1;
+    const char* ov = getenv("LBM_ADJOINT_OVERLAP");  // "0": one buffer, in order (measurement and tests)
+    const bool overlap = A->nbuf == 2 && nseg > 1 && !(ov && ov[0] == '0');
     if (overlap) {
         ADJ_TRY(hipEventRecord(A->ev_fwd, s));
         ADJ_TRY(hipStreamWaitEvent(A->side, A->ev_fwd, 0));
