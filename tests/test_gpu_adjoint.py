@@ -145,7 +145,7 @@ GOLD = os.path.join(GOLDEN, "adjoint_c5_512sq_500steps.json")
 def test_adjoint_workload_against_fp64_central_differences():
     """512 x 512, 500 steps, checkpoint every 50: misfit-loss gradients with
     respect to D, u, p, C0 and S against FP64 central differences of the
-    oracle (spec bound 1e-4 relative)."""
+    oracle (bound 1e-4 relative)."""
     gold = json.load(open(GOLD))
     hid = synth.config("c5_512sq_hidden")
     ev = synth.config("c5_512sq_eval")
