@@ -66,10 +66,17 @@ __device__ __forceinline__ float ldf(const float* base, OFF boff)
 {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
 }
-template <typename OFF, typename T>
+// Output store; NT: non-temporal (the line is not kept in L2 for reuse), for
+// grids whose state does not fit the Infinity Cache, so that the L2 keeps the
+// input lines that neighbouring tiles read again.
+template <bool NT, typename OFF, typename T>
 __device__ __forceinline__ void stv(T* base, OFF boff, T v)
 {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+    T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // BF16 split of C for the split-BF16 fractional term: hi = bf16(c),
@@ -223,7 +230,7 @@ __device__ inline void collide_x_pair(const CollideConsts& cc, const float (&f)[
 // ---------------------------------------------------------------------------
 // 2D D2Q5 fused kernel.  Rows move through a ring of D slots: while row y + 1
 // is collided, the loads of rows y + 2 .. y + D are in flight.
-template <bool HAS_S, bool PACK, bool VAR, typename OFF>
+template <bool HAS_S, bool PACK, bool VAR, bool NT, typename OFF>
 __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
                                                          float* __restrict__ fout, const float* __restrict__ Phi,
                                                          const float* __restrict__ S, float* __restrict__ Cout,
@@ -339,11 +346,11 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
                 float c = 0.f;
 #pragma unroll
                 for (int i = 0; i < 5; ++i) {
-                    stv(fout + i * nodes, b, f[i]);
+                    stv<NT>(fout + i * nodes, b, f[i]);
                     c += f[i];
                 }
-                stv(Cout, b, c);
-                if (PACK) stv(Cpout, b, pack_hilo(c));
+                stv<NT>(Cout, b, c);
+                if (PACK) stv<NT>(Cpout, b, pack_hilo(c));
             }
             prev3 = cur[3];
 #pragma unroll
@@ -369,7 +376,7 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
 // planes (the loads of planes z + 2 .. z + D are in flight while plane z + 1
 // is collided).  f*_3 / f*_4 cross rows through LDS, double-buffered by plane
 // parity so one barrier per plane suffices.
-template <int NY, bool HAS_S, bool PACK, bool VAR, typename OFF>
+template <int NY, bool HAS_S, bool PACK, bool VAR, bool NT, typename OFF>
 __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, const float* __restrict__ fin,
                                                              float* __restrict__ fout, const float* __restrict__ Phi,
                                                              const float* __restrict__ S, float* __restrict__ Cout,
@@ -491,11 +498,11 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
                 float c = 0.f;
 #pragma unroll
                 for (int i = 0; i < 7; ++i) {
-                    stv(fout, bo + i * fb, f[i]);
+                    stv<NT>(fout, bo + i * fb, f[i]);
                     c += f[i];
                 }
-                stv(Cout, bo, c);
-                if (PACK) stv(Cpout, bo, pack_hilo(c));
+                stv<NT>(Cout, bo, c);
+                if (PACK) stv<NT>(Cpout, bo, pack_hilo(c));
             }
             prev5 = cur[5];
 #pragma unroll
@@ -598,27 +605,21 @@ unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 // Calls f(integral_constant<bool, a>, ..., ...) for the run-time flags a, b, c:
 // picks one of the eight instantiations of a kernel template.
 template <typename F>
-void with_flags(bool a, bool b, bool c, F&& f)
+void with_bool(bool v, F&& f)
 {
-    using T = std::true_type;
-    using N = std::false_type;
-    if (a) {
-        if (b) {
-            if (c) f(T{}, T{}, T{});
-            else f(T{}, T{}, N{});
-        } else {
-            if (c) f(T{}, N{}, T{});
-            else f(T{}, N{}, N{});
-        }
-    } else {
-        if (b) {
-            if (c) f(N{}, T{}, T{});
-            else f(N{}, T{}, N{});
-        } else {
-            if (c) f(N{}, N{}, T{});
-            else f(N{}, N{}, N{});
-        }
-    }
+    if (v)
+        f(std::true_type{});
+    else
+        f(std::false_type{});
+}
+
+// f(integral_constant<bool, a>, ..., integral_constant<bool, d>)
+template <typename F>
+void with_flags(bool a, bool b, bool c, bool d, F&& f)
+{
+    with_bool(a, [&](auto A) {
+        with_bool(b, [&](auto B) { with_bool(c, [&](auto C) { with_bool(d, [&](auto D) { f(A, B, C, D); }); }); });
+    });
 }
 
 // March length forced by LBM_COLLIDE_ROWS (tuning; 0 = automatic): rows per
@@ -640,6 +641,15 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
     // space-dependent diffusion tensor and wall values (both fields present)
     const bool var = cc.dB != nullptr;
     if (var && !cc.Cw) return hipErrorInvalidValue;
+    // Non-temporal output stores once a step's traffic exceeds the 256 MB
+    // Infinity Cache (below it, the next step reads the outputs from there).
+    // Measured: 4096^2 177 -> 172 us, 256^3 303 -> 293 us; 1024^2 11.7 ->
+    // 15.6 us if used there.  LBM_COLLIDE_NT = 0 / 1 forces it (tuning).
+    bool nt = nodes_of(cc) * (2 * cc.Q + cc.dim + 1) * 4 > ((int64_t)256 << 20);
+    if (const char* e = getenv("LBM_COLLIDE_NT")) {
+        if (e[0] == '0') nt = false;
+        if (e[0] == '1') nt = true;
+    }
     if (cc.dim == 2) {
         const int nx = cc.n[0], ny = cc.n[1];
         const int strips = (nx + kStrip - 1) / kStrip;
@@ -658,11 +668,13 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out, rows,
                                strips, waves);
         };
-        with_flags(S != nullptr, Cp_out != nullptr, var, [&](auto hs, auto pk, auto vr) {
+        with_flags(S != nullptr, Cp_out != nullptr, var, nt, [&](auto hs, auto pk, auto vr, auto ntc) {
+            constexpr bool HS = decltype(hs)::value, PK = decltype(pk)::value, VR = decltype(vr)::value,
+                           NT = decltype(ntc)::value;
             if (small)
-                go(collide_stream_2d<decltype(hs)::value, decltype(pk)::value, decltype(vr)::value, uint32_t>);
+                go(collide_stream_2d<HS, PK, VR, NT, uint32_t>);
             else
-                go(collide_stream_2d<decltype(hs)::value, decltype(pk)::value, decltype(vr)::value, uint64_t>);
+                go(collide_stream_2d<HS, PK, VR, NT, uint64_t>);
         });
         return hipGetLastError();
     }
@@ -671,7 +683,7 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
     // neighbour on the same XCD has fetched.  At 256^3, 313 us against 322
     // with 16-row workgroups; the space-dependent variant (9 more values per
     // ring plane, up to 256 VGPRs) also needs the smaller workgroup.
-    auto launch3d = [&](auto ny_c, auto hs, auto pk, auto vr) {
+    auto launch3d = [&](auto ny_c, auto hs, auto pk, auto vr, auto ntc) {
         constexpr int NY = decltype(ny_c)::value;
         const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
         const int sx = (nx + kStrip - 1) / kStrip;
@@ -689,15 +701,18 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         const int chunks = (nz + planes - 1) / planes;
         const int64_t blocks = (int64_t)sx * sy * chunks;
         if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-        constexpr bool HS = decltype(hs)::value, PK = decltype(pk)::value, VR = decltype(vr)::value;
-        auto kern = small ? collide_stream_3d<NY, HS, PK, VR, uint32_t> : collide_stream_3d<NY, HS, PK, VR, uint64_t>;
+        constexpr bool HS = decltype(hs)::value, PK = decltype(pk)::value, VR = decltype(vr)::value,
+                       NT = decltype(ntc)::value;
+        auto kern =
+            small ? collide_stream_3d<NY, HS, PK, VR, NT, uint32_t> : collide_stream_3d<NY, HS, PK, VR, NT, uint64_t>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out,
                            planes, sx, sy);
         return hipSuccess;
     };
     hipError_t e = hipSuccess;
-    with_flags(S != nullptr, Cp_out != nullptr, var,
-               [&](auto hs, auto pk, auto vr) { e = launch3d(std::integral_constant<int, 8>{}, hs, pk, vr); });
+    with_flags(S != nullptr, Cp_out != nullptr, var, nt, [&](auto hs, auto pk, auto vr, auto ntc) {
+        e = launch3d(std::integral_constant<int, 8>{}, hs, pk, vr, ntc);
+    });
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

@@ -372,12 +372,14 @@ bool graphs_enabled()
     return !(v && v[0] == '0');
 }
 
-void graph_key(int (&k)[3])
+void graph_key(int (&k)[4])
 {
     k[0] = lbm::tile_choice("LBM_FP32_TILE");
     k[1] = lbm::tile_choice("LBM_BF16_TILE");
     const char* r = getenv("LBM_COLLIDE_ROWS");
     k[2] = r ? atoi(r) : 0;
+    const char* t = getenv("LBM_COLLIDE_NT");
+    k[3] = t ? 1 + (t[0] == '1') + 2 * (t[0] == '0') : 0;
 }
 
 void drop_graph(lbm_fade* h)
@@ -831,10 +833,10 @@ int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream)
     hipStream_t s = as_stream(stream);
     const int every = h->params.nonfinite_check_every;
     if (every == 0 && n >= kGraphSteps && graphs_enabled()) {
-        int key[3];
+        int key[4];
         graph_key(key);
         if (!h->gexec || h->gS != h->S || h->gdB != h->cc.dB || key[0] != h->gkey[0] || key[1] != h->gkey[1] ||
-            key[2] != h->gkey[2]) {
+            key[2] != h->gkey[2] || key[3] != h->gkey[3]) {
             rc = build_step_graph(h);
             if (rc) return rc;
         }

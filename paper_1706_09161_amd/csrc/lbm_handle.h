@@ -50,7 +50,7 @@ struct lbm_fade {
     int gcur = 0;                   // f[gcur] holds the populations the graph starts from
     const float* gS = nullptr;      // source pointer the graph was captured with
     const float* gdB = nullptr;     // space-dependent field pointer the graph was captured with
-    int gkey[3] = {0, 0, 0};        // tuning variables at capture (FP32 tile, BF16 tile, collide rows)
+    int gkey[4] = {0, 0, 0, 0};     // tuning variables at capture (FP32 tile, BF16 tile, collide rows, stores)
 };
 
 namespace lbm {

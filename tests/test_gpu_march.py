@@ -5,7 +5,8 @@ through LBM_COLLIDE_ROWS to short, long, odd and grid-exceeding values give
 the populations and C of the default launch bit for bit, on ragged grids
 (partial 64-column strips, a last chunk shorter than the march), with and
 without a source, in FP32 and split-BF16 (which also writes the packed C) and
-with the space-dependent fields.
+with the space-dependent fields.  The same holds for the non-temporal output
+stores that large grids use (forced here through LBM_COLLIDE_NT).
 """
 import os
 
@@ -56,11 +57,14 @@ def test_march_length_does_not_change_the_result(case, monkeypatch):
         Cw = synth.random_wall_values(cfg, seed=73).astype(np.float32)
     steps = 13  # one replay of the 10-step graph and three single steps
     monkeypatch.delenv("LBM_COLLIDE_ROWS", raising=False)
+    monkeypatch.setenv("LBM_COLLIDE_NT", "0")
     f_ref, C_ref = _run(cfg, precision, S, D, Cw, steps)
     assert np.isfinite(C_ref).all()
-    for m in marches:
-        monkeypatch.setenv("LBM_COLLIDE_ROWS", str(m))
+    runs = [(str(m), "0") for m in marches] + [("0", "1"), (str(marches[1]), "1")]
+    for rows, nt in runs:
+        monkeypatch.setenv("LBM_COLLIDE_ROWS", rows)
+        monkeypatch.setenv("LBM_COLLIDE_NT", nt)
+        assert os.environ["LBM_COLLIDE_NT"] == nt
         f, C = _run(cfg, precision, S, D, Cw, steps)
-        assert np.array_equal(f.view(np.uint32), f_ref.view(np.uint32)), m
-        assert np.array_equal(C.view(np.uint32), C_ref.view(np.uint32)), m
-    assert os.environ.get("LBM_COLLIDE_ROWS") == str(marches[-1])
+        assert np.array_equal(f.view(np.uint32), f_ref.view(np.uint32)), (rows, nt)
+        assert np.array_equal(C.view(np.uint32), C_ref.view(np.uint32)), (rows, nt)
