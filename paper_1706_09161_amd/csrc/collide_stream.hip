@@ -658,7 +658,9 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         // march on the same XCD mostly has in L2 already).  Measured on
         // MI355X (4 / 8 / 16 / 32 rows): 512^2 5.0 / 6.8 / 9.8 / 15.6 us,
         // 1024^2 11.7 / 11.5 / 11.8 / 17.0, 2048^2 33.6 / 36.3 / 35.5 / 34.9,
-        // 4096^2 182 / 180 / 175 / 175.
+        // 4096^2 182 / 180 / 175 / 175.  Shorter marches (2 or 3 rows) time
+        // faster per kernel at 512^2 (5.8 us) but the 500-step 512^2 run is
+        // slower with them (7.32 ms against 7.11 with 4 rows).
         int rows = collide_rows_override();
         if (rows <= 0) rows = (int64_t)nx * ny >= ((int64_t)1 << 23) ? 16 : 4;
         const int chunks = (ny + rows - 1) / rows;
