@@ -831,15 +831,25 @@ hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s)
     default: break;
     }
     // Register-ring kernel: wavefront tiles of 32 x 256 outputs, 4 line blocks
-    // per workgroup, when that gives >= 512 workgroups; otherwise tiles of
-    // 32 x 128 (two workgroups per CU) with k split 4 ways (measured best at
-    // 512^2 and 1024^2).
+    // per workgroup, when that gives >= 512 workgroups (in 3D only when 256
+    // divides every axis: no part-empty tiles); otherwise in 3D tiles of
+    // 32 x 128 with 2 line blocks and k split 2 ways, in 2D tiles of 32 x 128
+    // with k split 4 ways.  Measured on MI355X (kernel trace, us, against the
+    // other choice): 64^3 8.9 (11.1), 96^3 14.5 (19.9), 128^3 21.2 (30.6),
+    // 320^3 406 (491), 384^3 579 (664); 256^3 128 (142); 2D 512^2 9.0 (11.3),
+    // 1024^2, 1536^2 51.0 (53.3).
     {
+        bool batched = false, whole = true;
+        for (int a = 0; a < L.naxes; ++a) {
+            batched = batched || (!L.lay[a].contiguous && L.lay[a].batches > 1);
+            whole = whole && L.op[a].n % 256 == 0;
+        }
         FracLaunch T = L;
         int64_t grid = 0;
         size_t lds = 0;
         ring_grid<8, 4, 1>(T, grid, lds);
-        if (grid >= 512) return run_ring<8, 4, 1, 4>(L, s);
+        if (grid >= 512 && (!batched || whole)) return run_ring<8, 4, 1, 4>(L, s);
+        if (batched) return run_ring<4, 2, 2, 4>(L, s);
         return run_ring<4, 1, 4, 4>(L, s);
     }
 }
