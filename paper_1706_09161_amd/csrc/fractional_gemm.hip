@@ -651,16 +651,20 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
     if constexpr (KSPLIT > 1) {
         __syncthreads();  // every wavefront is done with the window
         float* red = win;
+        u_lo = wk * (U / KSPLIT);
+        u_hi = u_lo + U / KSPLIT;
+        // the units other k shares sum go through LDS; a wavefront's own
+        // units stay in registers (same fixed summation order, s = 0, 1, ...)
 #pragma unroll
         for (int c = 0; c < NBJ; ++c)
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
+                const int u = 4 * c + r4;
+                if (u >= u_lo && u < u_hi) continue;
                 float4 v = make_float4(acc[c][4 * r4], acc[c][4 * r4 + 1], acc[c][4 * r4 + 2], acc[c][4 * r4 + 3]);
                 *reinterpret_cast<float4*>(red + (((wave * NBJ + c) * 4 + r4) * 64 + lane) * 4) = v;
             }
         __syncthreads();
-        u_lo = wk * (U / KSPLIT);
-        u_hi = u_lo + U / KSPLIT;
 #pragma unroll
         for (int c = 0; c < NBJ; ++c)
 #pragma unroll
@@ -671,7 +675,9 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
 #pragma unroll
                 for (int s = 0; s < KSPLIT; ++s) {
                     const float4 v =
-                        *reinterpret_cast<const float4*>(red + ((((wl * KSPLIT + s) * NBJ + c) * 4 + r4) * 64 + lane) * 4);
+                        s == wk ? make_float4(acc[c][4 * r4], acc[c][4 * r4 + 1], acc[c][4 * r4 + 2], acc[c][4 * r4 + 3])
+                                : *reinterpret_cast<const float4*>(
+                                      red + ((((wl * KSPLIT + s) * NBJ + c) * 4 + r4) * 64 + lane) * 4);
                     sum.x += v.x;
                     sum.y += v.y;
                     sum.z += v.z;

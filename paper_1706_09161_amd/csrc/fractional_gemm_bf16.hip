@@ -655,16 +655,20 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     if constexpr (KSPLIT > 1) {
         __syncthreads();  // every wavefront is done with the pair-word window
         float* red = reinterpret_cast<float*>(pwh);
+        c_lo = wk * (NBJ / KSPLIT);
+        c_hi = c_lo + NBJ / KSPLIT;
+        // blocks other k shares sum go through LDS; a wavefront's own blocks
+        // stay in registers (same fixed summation order, s = 0, 1, ...)
 #pragma unroll
-        for (int c = 0; c < NBJ; ++c)
+        for (int c = 0; c < NBJ; ++c) {
+            if (c >= c_lo && c < c_hi) continue;
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 float4 v = make_float4(acc[c][4 * r4], acc[c][4 * r4 + 1], acc[c][4 * r4 + 2], acc[c][4 * r4 + 3]);
                 *reinterpret_cast<float4*>(red + (((wave * NBJ + c) * 4 + r4) * 64 + lane) * 4) = v;
             }
+        }
         __syncthreads();
-        c_lo = wk * (NBJ / KSPLIT);
-        c_hi = c_lo + NBJ / KSPLIT;
 #pragma unroll
         for (int c = 0; c < NBJ; ++c) {
             if (c < c_lo || c >= c_hi) continue;
@@ -674,7 +678,9 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
 #pragma unroll
                 for (int s = 0; s < KSPLIT; ++s) {
                     const float4 v =
-                        *reinterpret_cast<const float4*>(red + ((((wl * KSPLIT + s) * NBJ + c) * 4 + r4) * 64 + lane) * 4);
+                        s == wk ? make_float4(acc[c][4 * r4], acc[c][4 * r4 + 1], acc[c][4 * r4 + 2], acc[c][4 * r4 + 3])
+                                : *reinterpret_cast<const float4*>(
+                                      red + ((((wl * KSPLIT + s) * NBJ + c) * 4 + r4) * 64 + lane) * 4);
                     sum.x += v.x;
                     sum.y += v.y;
                     sum.z += v.z;
