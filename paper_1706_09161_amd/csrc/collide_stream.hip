@@ -20,17 +20,22 @@
 // multiple of 64 (its loads and stores are whole 128-byte lines) and marches
 // up the y axis: the collision of row y+1 is computed once, its f*_4 is used
 // for row y and its f*_3 for row y+2.  The rows read ahead stop at the first
-// row past the chunk (the last block of a march refills only what it needs).  f*_1 / f*_2 cross columns by lane
-// shuffles; at the strip's two edges lanes 0 and 63 also read the node just
-// outside the strip and compute the one population that crosses (one row of
-// the collision operator).  Every node is collided once (plus 2 halo rows per
-// march), every population is read once and written once: (2Q + d + 1) * 4
-// bytes per node from HBM (52 B for D2Q5).
+// row past the chunk (the last block of a march refills only what it needs).
+// f*_1 / f*_2 cross columns by lane shuffles; at the strip's two edges lanes
+// 0 and 63 also read the node just outside the strip and compute the one
+// population that crosses (one row of the collision operator).  Every node is
+// collided once (plus 2 halo rows per march), every population is read once
+// and written once: (2Q + d + 1) * 4 bytes per node from HBM (52 B for D2Q5).
 //
 // 3D (D3Q7): a workgroup of NY wavefronts covers 64 x (NY - 2) nodes of one z
 // plane (one wave per y row, rows 0 and NY-1 halo, the x edges as in 2D) and
 // marches along z; f*_3/f*_4 cross rows through LDS, f*_5/f*_6 cross planes in
 // registers.
+//
+// Both kernels deal their tiles to the XCDs in contiguous ranges (halo lines
+// shared in one L2), store their outputs non-temporally once a step's traffic
+// exceeds the Infinity Cache, and round every node alike whatever the launch
+// shape (explicit fmaf only), so results do not depend on the march length.
 //
 // Offsets are 32-bit byte offsets from uniform base pointers (one VALU add per
 // address) while every array fits in 4 GiB, 64-bit otherwise.
