@@ -148,21 +148,25 @@ def measured_traffic():
         return None
 
 
-def profile_run(torch, LbmFade, synth, reps: int = 20):
+def profile_run(torch, LbmFade, synth, workload: str = WORKLOAD, reps: int = 20):
     """Launch sequence for rocprofv3 (trace or counters): a plain 256 MiB copy
     (the calibration of FETCH_SIZE / WRITE_SIZE), then, per precision, `reps`
     launches of the fractional-term GEMM on the solver's own C and `reps`
-    steps of the benchmark workload."""
+    steps of the workload (the benchmark's by default; with its source, if it
+    has one)."""
     a = torch.ones(64 * 1024 * 1024, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    cfg = synth.config(WORKLOAD)
+    cfg = synth.config(workload)
     C0 = torch.from_numpy(synth.initial_C(cfg).astype(np.float32)).cuda()
+    S = synth.source(cfg)
     for precision in ("fp32", "bf16x3"):
         with LbmFade.from_config(cfg, precision=precision) as s:
             s.set_C(C0)
+            if S is not None:
+                s.set_source(S.astype(np.float32))
             out = torch.empty((cfg["dim"],) + tuple(C0.shape), device="cuda")
             for _ in range(reps):
                 s.apply_phi(None, out=out)
@@ -229,6 +233,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the launch sequence profiled by rocprofv3 (copy calibration, GEMM, steps); no JSON")
+    ap.add_argument("--profile-workload", default=WORKLOAD,
+                    help="workload of --profile-run (a synth configuration name, e.g. c3_256cube)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -244,7 +250,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.profile_run:
-        profile_run(torch, LbmFade, synth)
+        profile_run(torch, LbmFade, synth, args.profile_workload)
         return
     cfg = synth.config(WORKLOAD)
     d = cfg["dim"]
