@@ -142,3 +142,79 @@ def test_walk_against_lb_validation_1():
     rel2d = np.abs(dens[well] - Cn[well]) / Cn[well]
     print(f"[gpu-rw] 2D density where C > 20% of max: median rel diff {np.median(rel2d):.3f}", flush=True)
     assert np.median(rel2d) < 0.03
+
+
+def _lb_vs_walk(dim, n, L, dx, dt, T, alpha, p, center, s0, seed, N=4_000_000, dt_rw=1e-3):
+    """GPU LB (BGK, D = 0.5 Id, g = 1, u = 0, walls 0) and GPU walk from the
+    same resolved Gaussian hill: the LB field normalised by its initial mass,
+    the walk's density per node, their surviving masses."""
+    from paper_1706_09161_amd import LbmFade
+
+    cfg = dict(dim=dim, n=[n] * dim, dx=dx, dt=dt, alpha=list(alpha), p=list(p), g=[1.0] * dim,
+               D=(0.5 * np.eye(dim)).tolist(), u=[0.0] * dim, collision="BGK", tau_free=[1.0] * 4, tau0=1.0,
+               c_wall=0.0)
+    C0 = synth.paper_gaussian(cfg, center, sigma0=s0, C0=1.0)
+    with LbmFade.from_config(cfg) as s:
+        s.set_C(C0.astype(np.float32))
+        s.step(int(round(T / dt)))
+        C = s.get_C(device=False).astype(np.float64)
+    mass0 = C0.sum() * dx ** dim
+    W = _rw(dim, [0.0] * dim, [L] * dim, alpha=list(alpha), p=list(p), D=[0.5] * dim, dt=dt_rw, seed=seed)
+    x, a = W.init_gaussian(center, s0, N)
+    W.walk(x, a, int(round(T / dt_rw)))
+    dens = W.histogram(x, a, [n] * dim, dx).cpu().numpy().astype(np.float64) / N / dx ** dim
+    surv = float(a.float().mean())
+    return C / mass0, dens, C.sum() * dx ** dim / mass0, surv
+
+
+def test_walk_against_lb_validation_2():
+    """The paper's validation 2 (Sec. 3.2): Omega = [0, 2]^2, alpha = 1.2,
+    p = (0.35, 0.5) (skewed along x1 only), D = 0.5 Id, BGK, dx = 0.01 (201
+    nodes), dt = 5e-5, to t = 0.6.  LB and walk agree on the surviving mass
+    and both marginals, and both show what the paper describes: with p1 < 1/2
+    the maximum moves to larger x1 although u = 0, and the x1-profile decays
+    more slowly to the left of its maximum than to the right."""
+    n, dx = 201, 0.01
+    Cn, dens, mass_lb, surv = _lb_vs_walk(2, n, 2.0, dx, 5e-5, 0.6, (1.2, 1.2), (0.35, 0.5), (1.0, 1.0), 0.05,
+                                          seed=2025)
+    N = 4_000_000
+    print(f"[gpu-rw] validation 2: survival {surv:.5f}, LB mass {mass_lb:.5f}", flush=True)
+    assert abs(surv - mass_lb) < 4 * math.sqrt(surv * (1 - surv) / N) + 2e-3
+    xs = np.arange(n) * dx
+    prof = {}
+    for ax, name in ((0, "x1"), (1, "x2")):
+        m_lb, m_rw = Cn.sum(axis=ax) * dx, dens.sum(axis=ax) * dx
+        err = np.linalg.norm(m_lb - m_rw) / np.linalg.norm(m_lb)
+        print(f"[gpu-rw] marginal along {name}: rel L2 {err:.2e}", flush=True)
+        assert err < 0.02
+        prof[name] = (m_lb, m_rw)
+    for m in prof["x1"]:
+        k = int(np.argmax(m))
+        print(f"[gpu-rw] x1 marginal: peak at {xs[k]:.2f}; 0.3 and 0.5 either side of it: "
+              f"{m[k - 30]:.3f} / {m[k + 30]:.3f}, {m[k - 50]:.3f} / {m[k + 50]:.3f}", flush=True)
+        assert xs[k] > 1.0 + 2 * dx
+        assert m[k - 30] > m[k + 30] and m[k - 50] > m[k + 50]
+    m2 = prof["x2"][0]
+    assert abs(xs[int(np.argmax(m2))] - 1.0) <= dx  # p2 = 1/2: no shift along x2
+
+
+def test_walk_against_lb_validation_3():
+    """The paper's validation 3 (Sec. 3.2): Omega = [0, 1]^3, alpha = 1.2,
+    p = (0.35, 0.5, 0.5), D = 0.5 Id, BGK, dx = 0.0125 (81 nodes per axis),
+    dt = 3e-5, to t = 0.21: surviving mass, the x1-marginal, and its maximum
+    moved to larger x1."""
+    n, dx = 81, 0.0125
+    Cn, dens, mass_lb, surv = _lb_vs_walk(3, n, 1.0, dx, 3e-5, 0.21, (1.2, 1.2, 1.2), (0.35, 0.5, 0.5),
+                                          (0.5, 0.5, 0.5), 0.05, seed=2026)
+    N = 4_000_000
+    print(f"[gpu-rw] validation 3: survival {surv:.5f}, LB mass {mass_lb:.5f}", flush=True)
+    assert abs(surv - mass_lb) < 4 * math.sqrt(surv * (1 - surv) / N) + 3e-3
+    xs = np.arange(n) * dx
+    for axes, name in (((0, 1), "x1"), ((0, 2), "x2")):
+        m_lb, m_rw = Cn.sum(axis=axes) * dx * dx, dens.sum(axis=axes) * dx * dx
+        err = np.linalg.norm(m_lb - m_rw) / np.linalg.norm(m_lb)
+        print(f"[gpu-rw] 3D marginal along {name}: rel L2 {err:.2e}", flush=True)
+        assert err < 0.03
+        if name == "x1":
+            for m in (m_lb, m_rw):
+                assert xs[int(np.argmax(m))] > 0.5 + dx
