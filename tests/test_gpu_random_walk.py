@@ -142,6 +142,12 @@ def test_walk_against_lb_validation_1():
     rel2d = np.abs(dens[well] - Cn[well]) / Cn[well]
     print(f"[gpu-rw] 2D density where C > 20% of max: median rel diff {np.median(rel2d):.3f}", flush=True)
     assert np.median(rel2d) < 0.03
+    # most paths leave through the walls normal to x1, where alpha_1 = 1.5
+    # makes long jumps likely (a dead particle keeps its first position outside)
+    xs, dead = x.cpu().numpy(), a.cpu().numpy() == 0
+    out1 = dead & ((xs[0] <= 0.0) | (xs[0] >= 2.0))
+    print(f"[gpu-rw] exits through the x1 walls: {out1.sum()} of {dead.sum()}", flush=True)
+    assert out1.sum() > 0.7 * dead.sum()
 
 
 def _lb_vs_walk(dim, n, L, dx, dt, T, alpha, p, center, s0, seed, N=4_000_000, dt_rw=1e-3):

@@ -137,3 +137,16 @@ def test_histogram_counts_every_living_particle_once(oracle_lib):
     assert h.sum() == al.sum() and h.shape == (101, 201)
     j = np.floor(x[0][al == 1] / 0.01 + 0.5).astype(int)
     assert np.array_equal(np.bincount(j, minlength=201), h.sum(axis=0))
+
+
+def test_exits_mostly_through_the_super_diffusive_walls(oracle_lib):
+    """The paper's validation 1 (Sec. 3.2): with alpha = (1.5, 1.99) most
+    sample paths that leave [0, 2]^2 do so through the walls normal to x1."""
+    P = oracle_lib.rw_params(2, [0, 0], [2, 2], [1.5, 1.99], [0.5, 0.5], (0.5, 0.5), dt=1e-3, seed=2024)
+    x, al = oracle_lib.rw_init_gaussian(P, (1.0, 1.0), 0.05, 100000)
+    x, al = oracle_lib.rw_walk(P, x, al, 100)
+    dead = al == 0
+    out1 = dead & ((x[0] <= 0.0) | (x[0] >= 2.0))
+    out2 = dead & ~out1 & ((x[1] <= 0.0) | (x[1] >= 2.0))
+    assert dead.sum() > 1000 and out1.sum() + out2.sum() == dead.sum()
+    assert out1.sum() > 0.7 * dead.sum()
