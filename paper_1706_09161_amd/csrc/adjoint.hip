@@ -567,6 +567,12 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
         }
     }
     AdjointState* A = h->adj;
+    // a call that failed part-way may have left segment work on the side
+    // stream; it must not overlap this call's use of the buffers
+    if (A->side && hipStreamSynchronize(A->side) != hipSuccess) {
+        msg = "side stream of an earlier adjoint failed";
+        return LBM_EDEVICE;
+    }
     if (!alloc_state(h, A, n, K)) {
         msg = "allocation of the adjoint checkpoints failed";
         return LBM_ENOMEM;
