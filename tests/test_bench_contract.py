@@ -1,0 +1,32 @@
+"""bench.py's contract, the parts checkable without a GPU: it refuses more than
+one GPU with a message and exit status 2, and the committed HBM-counter
+summary of the FP32 fractional-term GEMM belongs to the GEMM sources built
+now (otherwise the bench line would report its traffic as null)."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_counter_summary_matches_the_gemm_sources():
+    b = _bench()
+    traffic = b.measured_traffic()
+    assert traffic is not None, "profiles/gemm_fp32__2d_1024sq_pmc.txt was taken from other GEMM sources"
+    # FETCH + WRITE per launch: within a few percent of the algorithmic 16 MiB
+    assert 0.95 * 16777216 <= traffic <= 1.5 * 16777216
