@@ -317,6 +317,38 @@ def test_full_size_sampled_step(name, precision):
     assert err <= (1e-5 if precision == "fp32" else 1e-4)
 
 
+@pytest.mark.parametrize("base,n,precision", [("c2_1024sq", [12416, 12416], "fp32"),
+                                              ("c3_256cube", [536, 536, 536], "fp32"),
+                                              ("c3_256cube", [536, 536, 536], "bf16x3")])
+def test_sampled_step_beyond_32bit_offsets(base, n, precision):
+    """The largest grids: 7 fields of more than 2^30 floats each, so the
+    kernels take their 64-bit offset variants (and the non-temporal stores of
+    grids beyond the Infinity Cache).  One GPU step after 3 is compared at
+    sampled nodes, the last node included, with the oracle's step from the
+    same populations."""
+    cfg = synth.config(base, n=n)
+    nodes = synth.nodes(cfg)
+    assert nodes * 7 * 4 >= 1 << 32
+    _banner(f"64-bit offsets {base} n={n} {precision}")
+    S = synth.source(cfg)
+    S32 = None if S is None else S.astype(np.float32)
+    with _solver(cfg, precision) as s:
+        s.set_C(synth.initial_C(cfg).astype(np.float32))
+        if S32 is not None:
+            s.set_source(S32)
+        s.step(3)
+        f = s.get_f(device=False).astype(np.float64)
+        s.step(1)
+        f1 = s.get_f(device=False).reshape(2 * cfg["dim"] + 1, -1)
+    pick = _sample_nodes(cfg, 200, 9)
+    assert pick[-1] == nodes - 1
+    ref = oracle.step_sampled(cfg, f, pick, S=None if S32 is None else S32.astype(np.float64))
+    got = f1[:, pick].astype(np.float64)
+    err = np.abs(got - ref).max() / np.abs(f).max()
+    print(f"[gpu-parity] 64-bit offsets {base} {precision}: sampled max err / max|f| = {err:.3e}", flush=True)
+    assert err <= (1e-5 if precision == "fp32" else 1e-4)
+
+
 @pytest.mark.parametrize("name", ["c4_4096sq", "c2_1024sq", "c3_256cube"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_full_size_phi_per_axis(name, precision):
