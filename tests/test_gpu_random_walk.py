@@ -224,3 +224,24 @@ def test_walk_against_lb_validation_3():
         if name == "x1":
             for m in (m_lb, m_rw):
                 assert xs[int(np.argmax(m))] > 0.5 + dx
+
+
+def test_empty_and_degenerate_inputs():
+    """No particles, no steps, sigma0 = 0 (every particle starts at the
+    centre), and a particle that starts on a wall (dead from the start, never
+    moved)."""
+    W = _rw(2, [0, 0], [1, 1], alpha=[1.5, 1.5], p=[0.5, 0.5], D=[0.1, 0.1], dt=1e-3, seed=3)
+    x, a = W.init_gaussian([0.5, 0.5], 0.1, 0)
+    W.walk(x, a, 10)
+    h = W.histogram(x, a, [11, 11], 0.1)
+    assert x.shape == (2, 0) and a.numel() == 0 and int(h.sum()) == 0
+    x, a = W.init_gaussian([0.5, 0.5], 0.0, 1000)
+    assert torch.all(x == 0.5) and torch.all(a == 1)
+    before = x.clone()
+    W.walk(x, a, 0)
+    assert torch.equal(x, before)
+    x, a = W.init_gaussian([0.0, 0.5], 0.0, 10)  # on the wall x1 = 0: outside the open box
+    assert torch.all(a == 0)
+    W.walk(x, a, 5)
+    assert torch.all(x[0] == 0.0) and torch.all(a == 0)
+    assert int(W.histogram(x, a, [11, 11], 0.1).sum()) == 0
