@@ -83,6 +83,8 @@ PHI_CASES = [
     (2, [200, 131], [1.05, 1.95], [0.0, 1.0]),
     (3, [21, 18, 13], [1.5, 1.6, 1.8], [0.5, 0.2, 0.9]),
     (3, [40, 33, 35], [1.2, 1.9, 1.4], [1.0, 0.0, 0.6]),
+    (2, [70, 41], [2.0, 1.01], [0.3, 0.7]),              # alpha = 2 (local) and near 1 (heaviest tails)
+    (3, [17, 19, 21], [2.0, 2.0, 2.0], [0.5, 1.0, 0.0]),  # classical ADE on every axis
 ]
 
 
@@ -244,9 +246,11 @@ def test_end_to_end_small_workload_fp32():
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("dim,n,collision", [(2, [75, 58], "MRT"), (3, [24, 19, 21], "MRT"), (2, [41, 41], "BGK")])
-def test_end_to_end_random_problems(dim, n, collision):
-    cfg = synth.small(dim, n, seed=51, collision=collision, with_source=True, c_wall=0.1)
+@pytest.mark.parametrize("dim,n,collision,alpha", [(2, [75, 58], "MRT", None), (3, [24, 19, 21], "MRT", None),
+                                                   (2, [41, 41], "BGK", None), (2, [50, 43], "MRT", [2.0, 2.0]),
+                                                   (3, [20, 17, 15], "BGK", [2.0, 1.02, 2.0])])
+def test_end_to_end_random_problems(dim, n, collision, alpha):
+    cfg = synth.small(dim, n, seed=51, collision=collision, with_source=True, c_wall=0.1, alpha=alpha)
     _banner(f"end-to-end dim={dim} n={n} {collision}")
     C0 = synth.initial_C(cfg).astype(np.float32)
     S = synth.source(cfg).astype(np.float32)
