@@ -175,6 +175,25 @@ def profile_run(torch, LbmFade, synth, workload: str = WORKLOAD, reps: int = 20)
     log("profile run done")
 
 
+def profile_adjoint(torch, LbmFade, synth):
+    """Launch sequence for a rocprofv3 kernel trace of the adjoint: on the
+    512^2 adjoint workload, 500 forward steps and then lbm_fade_adjoint(500
+    steps, checkpoint every 50), each twice (the first pass allocates the
+    checkpoints and captures the step graph)."""
+    cfg = synth.config("c5_512sq_eval")
+    steps, K = cfg["steps"], cfg["ckpt_every"]
+    C0 = torch.from_numpy(synth.initial_C(cfg).astype(np.float32)).cuda()
+    gC = torch.from_numpy(np.random.default_rng(5).standard_normal(synth.shape(cfg)).astype(np.float32)).cuda()
+    with LbmFade.from_config(cfg, precision="fp32") as s:
+        for _ in range(2):
+            s.set_C(C0)
+            s.step(steps)
+            s.set_C(C0)
+            s.adjoint(steps, K, gC)
+        torch.cuda.synchronize()
+    log("adjoint profile run done")
+
+
 def adjoint_ratio(torch, LbmFade, synth):
     """Wall time of lbm_fade_adjoint(500 steps, checkpoint every 50) over that of
     500 forward steps on the 512^2 adjoint workload (misfit gradient point)."""
@@ -235,6 +254,8 @@ def main():
                     help="only the launch sequence profiled by rocprofv3 (copy calibration, GEMM, steps); no JSON")
     ap.add_argument("--profile-workload", default=WORKLOAD,
                     help="workload of --profile-run (a synth configuration name, e.g. c3_256cube)")
+    ap.add_argument("--profile-adjoint", action="store_true",
+                    help="only the adjoint launch sequence (512^2: 500 steps forward, then the adjoint), twice; no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -251,6 +272,9 @@ def main():
         sys.exit(1)
     if args.profile_run:
         profile_run(torch, LbmFade, synth, args.profile_workload)
+        return
+    if args.profile_adjoint:
+        profile_adjoint(torch, LbmFade, synth)
         return
     cfg = synth.config(WORKLOAD)
     d = cfg["dim"]

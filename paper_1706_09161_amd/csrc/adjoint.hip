@@ -84,6 +84,65 @@ __global__ void broadcast_kernel(const float* __restrict__ gC, float* __restrict
     for (int i = 0; i < Q; ++i) fbar[i * nodes + x] = g;
 }
 
+// The reversed fractional term of every axis at node x: returns
+// sum_mu K_mu^T Phibar_mu = sum_mu (p U + (1 - p) L), and sets red[mu] to the
+// node's part of <Phibar_mu, (dK_mu/dp) C>: (U - L)(x) C(x) plus
+// Phibar_mu(x) (dc0_j C(x_0) + dcN_j C(x_N)), j = x's index along the line
+// and x_0, x_N the line's wall nodes (the p-derivatives of the boundary
+// columns).
+struct RevConsts {
+    int n[3];
+    int64_t stride[3];
+    float p[3];
+    const float* dc0[3];
+    const float* dcN[3];
+};
+
+// sum_mu K_mu^T Phibar_mu at node x from the two triangular products
+template <int D>
+__device__ inline float kt_at(const RevConsts& rc, const float* __restrict__ tu, const float* __restrict__ tl,
+                              int64_t x, int64_t nodes)
+{
+    float kt = 0.f;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const float u = tu[mu * nodes + x], l = tl[mu * nodes + x];
+        kt += fmaf(rc.p[mu], u - l, l);
+    }
+    return kt;
+}
+
+// red[mu] = the node's part of <Phibar_mu, (dK_mu/dp_mu) C> (x at grid coordinates c)
+template <int D>
+__device__ inline void p_terms(const RevConsts& rc, const float* __restrict__ tu, const float* __restrict__ tl,
+                               const float* __restrict__ phibar, const float* __restrict__ C, int64_t x,
+                               const int (&c)[3], int64_t nodes, double* red)
+{
+    const double Cx = (double)C[x];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const float u = tu[mu * nodes + x], l = tl[mu * nodes + x];
+        const int j = c[mu], N = rc.n[mu] - 1;
+        const double walls = (double)rc.dc0[mu][j] * (double)C[x - (int64_t)j * rc.stride[mu]] +
+                             (double)rc.dcN[mu][j] * (double)C[x + (int64_t)(N - j) * rc.stride[mu]];
+        red[mu] = ((double)u - (double)l) * Cx + (double)phibar[mu * nodes + x] * walls;
+    }
+}
+
+template <int D>
+__device__ inline float reversed_fractional(const RevConsts& rc, const float* __restrict__ tu,
+                                            const float* __restrict__ tl, const float* __restrict__ phibar,
+                                            const float* __restrict__ C, int64_t x, int64_t nodes, double (&red)[D])
+{
+    int c[3] = {0, 0, 0};
+    c[0] = (int)(x % rc.n[0]);
+    const int64_t r = x / rc.n[0];
+    c[1] = (int)(r % rc.n[1]);
+    c[2] = (int)(r / rc.n[1]);
+    p_terms<D>(rc, tu, tl, phibar, C, x, c, nodes, red);
+    return kt_at<D>(rc, tu, tl, x, nodes);
+}
+
 // Reverse of one step at every node (streaming + Dirichlet rule, collision,
 // equilibrium).  Writes fdir (the part of fbar^t that does not go through C),
 // Cbar (equilibrium part), Phibar, adds to dS, and per-workgroup FP64 partial
@@ -95,9 +154,25 @@ __global__ void broadcast_kernel(const float* __restrict__ gC, float* __restrict
 //     (dL/dLambda = M^-T (dL/dR) M^T; only the flux block of Lambda depends on D);
 //   dL/du_mu (d values);
 //   tr dL/dR = sum_i fbar*_i (f^eq_i - f_i) (BGK: R = I / lambda).
+// FUSED: fbar of the later step is not stored but formed where it is read,
+// fbar_i(y) = fdir'_i(y) + Cbar'(y) + sum_mu K_mu^T Phibar'_mu(y) (the moment
+// reversed; primes: that step's fields, the K^T products in tu / tl), and
+// the later step's p-gradient terms <Phibar'_mu, (dK_mu/dp_mu) C'> at x are
+// summed too (slots NV .. NV + d); otherwise fbar is read (the first step of
+// the sweep) and those slots add zero.
 // Grid: x across threads, y and z across workgroups (no integer division).
-template <int Q>
-__global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float* __restrict__ fbar,
+struct LaterStep {
+    const float* fbar;    // !FUSED
+    const float* fdir;    // FUSED: fields of the later step
+    const float* cbar;
+    const float* phibar;
+    const float* tu;
+    const float* tl;
+    const float* C;
+};
+
+template <int Q, bool FUSED>
+__global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, RevConsts rc, LaterStep ls,
                                                        const float* __restrict__ f, const float* __restrict__ Phi,
                                                        float* __restrict__ fdir, float* __restrict__ cbar,
                                                        float* __restrict__ phibar, float* __restrict__ dS,
@@ -107,10 +182,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
     constexpr int NV = d * d + d + 1;
     const int c[3] = {(int)(blockIdx.x * kBlock + threadIdx.x), (int)blockIdx.y, (int)blockIdx.z};
     const int64_t x = ((int64_t)c[2] * ac.n[1] + c[1]) * ac.n[0] + c[0];
-    double red[NV];
+    double red[NV + d];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) red[k] = 0.0;
+    for (int k = 0; k < NV + d; ++k) red[k] = 0.0;
     if (c[0] < ac.n[0]) {
+        if (FUSED) p_terms<d>(rc, ls.tu, ls.tl, ls.phibar, ls.C, x, c, nodes, red + NV);
         // adjoint of f*(x): pulled from the node each population moved to
         float fsb[Q];
 #pragma unroll
@@ -125,7 +201,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
                 continue;
             }
             const int64_t yi = ((int64_t)y[2] * ac.n[1] + y[1]) * ac.n[0] + y[0];
-            float g = fbar[(int64_t)i * nodes + yi];
+            const float cy = FUSED ? ls.cbar[yi] + kt_at<d>(rc, ls.tu, ls.tl, yi, nodes) : 0.f;
+            auto fbar_at = [&](int b) {
+                return FUSED ? ls.fdir[(int64_t)b * nodes + yi] + cy : ls.fbar[(int64_t)b * nodes + yi];
+            };
+            float g = fbar_at(i);
             // unknown populations at y (their sources lie outside) share its Dirichlet deficit
             int cnt = 0;
             float sum = 0.f;
@@ -135,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
                 const int src = y[mu] - (((b - 1) & 1) ? -1 : 1);
                 if (src < 0 || src >= ac.n[mu]) {
                     ++cnt;
-                    sum += fbar[(int64_t)b * nodes + yi];
+                    sum += fbar_at(b);
                 }
             }
             if (cnt > 0) g -= sum / (float)cnt;
@@ -200,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_node(AdjConsts ac, const float
         cbar[x] = cb;
     }
     const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum_store<NV, true>(red, part + blk * NV);  // running sum over the reverse sweep
+    block_sum_store<NV + d, true>(red, part + blk * (NV + d));  // running sum over the reverse sweep
 }
 
 // Reverse of the initial equilibrium f^0 = f^eq(C0', Phi(C0')): fbar^0 is the
@@ -249,44 +329,6 @@ __global__ __launch_bounds__(kBlock) void reduce_partials(const double* __restri
         __syncthreads();
     }
     if (threadIdx.x == 0) acc[off + v] += sh[0];
-}
-
-// The reversed fractional term of every axis at node x: returns
-// sum_mu K_mu^T Phibar_mu = sum_mu (p U + (1 - p) L), and sets red[mu] to the
-// node's part of <Phibar_mu, (dK_mu/dp) C>: (U - L)(x) C(x) plus
-// Phibar_mu(x) (dc0_j C(x_0) + dcN_j C(x_N)), j = x's index along the line
-// and x_0, x_N the line's wall nodes (the p-derivatives of the boundary
-// columns).
-struct RevConsts {
-    int n[3];
-    int64_t stride[3];
-    float p[3];
-    const float* dc0[3];
-    const float* dcN[3];
-};
-
-template <int D>
-__device__ inline float reversed_fractional(const RevConsts& rc, const float* __restrict__ tu,
-                                            const float* __restrict__ tl, const float* __restrict__ phibar,
-                                            const float* __restrict__ C, int64_t x, int64_t nodes, double (&red)[D])
-{
-    int c[3];
-    c[0] = (int)(x % rc.n[0]);
-    const int64_t r = x / rc.n[0];
-    c[1] = (int)(r % rc.n[1]);
-    c[2] = (int)(r / rc.n[1]);
-    const double Cx = (double)C[x];
-    float kt = 0.f;
-#pragma unroll
-    for (int mu = 0; mu < D; ++mu) {
-        const float u = tu[mu * nodes + x], l = tl[mu * nodes + x];
-        kt += fmaf(rc.p[mu], u - l, l);
-        const int j = c[mu], N = rc.n[mu] - 1;
-        const double walls = (double)rc.dc0[mu][j] * (double)C[x - (int64_t)j * rc.stride[mu]] +
-                             (double)rc.dcN[mu][j] * (double)C[x + (int64_t)(N - j) * rc.stride[mu]];
-        red[mu] = ((double)u - (double)l) * Cx + (double)phibar[mu * nodes + x] * walls;
-    }
-    return kt;
 }
 
 // fbar_i = fdir_i + Cbar + sum_mu K_mu^T Phibar_mu, and the per-workgroup FP64
@@ -359,9 +401,15 @@ struct AdjointState {
     hipStream_t side = nullptr;              // default priority, non-blocking
     hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
     float* fbar = nullptr;
+    // fdir, Cbar and Phibar of a step, two sets (by step parity): the kernel
+    // of step t reads step t + 1's set at neighbouring nodes
     float* fdir = nullptr;
     float* cbar = nullptr;
     float* phibar = nullptr;
+    float* fdir2 = nullptr;
+    float* cbar2 = nullptr;
+    float* phibar2 = nullptr;
+    float* Ckeep = nullptr;  // C of the first step of the segment swept last
     float* tu = nullptr;  // s W+^T Phibar_mu (d fields)
     float* tl = nullptr;  // s W-^T Phibar_mu (d fields)
     float* dS = nullptr;
@@ -377,7 +425,8 @@ void adjoint_free(AdjointState* a)
 {
     if (!a) return;
     void* ptrs[] = {a->ckpt, a->seg_f[0], a->seg_phi[0], a->seg_C[0], a->seg_f[1], a->seg_phi[1], a->seg_C[1],
-                    a->fbar, a->fdir, a->cbar, a->phibar, a->tu, a->tl, a->dS, a->part, a->part2, a->acc, a->opmem};
+                    a->fbar, a->fdir, a->cbar, a->phibar, a->fdir2, a->cbar2, a->phibar2, a->Ckeep,
+                    a->tu, a->tl, a->dS, a->part, a->part2, a->acc, a->opmem};
     for (void* p : ptrs) (void)hipFree(p);
     hipEvent_t evs[] = {a->ev_fwd, a->ev_rec[0], a->ev_rec[1], a->ev_rev[0], a->ev_rev[1]};
     for (hipEvent_t e : evs)
@@ -524,10 +573,13 @@ bool alloc_state(lbm_fade* h, AdjointState* A, int64_t n, int K)
         if (hipMalloc(&A->fbar, fq) != hipSuccess || hipMalloc(&A->fdir, fq) != hipSuccess ||
             hipMalloc(&A->cbar, sizeof(float) * nodes) != hipSuccess ||
             hipMalloc(&A->phibar, sizeof(float) * d * nodes) != hipSuccess ||
+            hipMalloc(&A->fdir2, fq) != hipSuccess || hipMalloc(&A->cbar2, sizeof(float) * nodes) != hipSuccess ||
+            hipMalloc(&A->phibar2, sizeof(float) * d * nodes) != hipSuccess ||
+            hipMalloc(&A->Ckeep, sizeof(float) * nodes) != hipSuccess ||
             hipMalloc(&A->tu, sizeof(float) * d * nodes) != hipSuccess ||
             hipMalloc(&A->tl, sizeof(float) * d * nodes) != hipSuccess ||
             hipMalloc(&A->dS, sizeof(float) * nodes) != hipSuccess ||
-            hipMalloc(&A->part, sizeof(double) * nb_node_max(h) * (3 * 3 + 3 + 1)) != hipSuccess ||
+            hipMalloc(&A->part, sizeof(double) * nb_node_max(h) * (3 * 3 + 3 + 1 + 3)) != hipSuccess ||
             hipMalloc(&A->part2, sizeof(double) * nb * 3) != hipSuccess ||
             hipMalloc(&A->acc, sizeof(double) * 64) != hipSuccess)
             return false;
@@ -601,11 +653,11 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
         ops2[d + mu] = A->opsL[mu];
         lays2[mu] = lays2[d + mu] = h->lays[mu];
     }
-    auto reversed_phi = [&]() -> hipError_t {
+    auto reversed_phi = [&](const float* pb) -> hipError_t {
         const float* in[2 * 3];
         float* outp[2 * 3];
         for (int mu = 0; mu < d; ++mu) {
-            in[mu] = in[d + mu] = A->phibar + (int64_t)mu * nodes;
+            in[mu] = in[d + mu] = pb + (int64_t)mu * nodes;
             outp[mu] = A->tu + (int64_t)mu * nodes;
             outp[d + mu] = A->tl + (int64_t)mu * nodes;
         }
@@ -635,11 +687,11 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     ADJ_TRY(hipMemsetAsync(A->dS, 0, sizeof(float) * nodes, s));
     // per-workgroup running sums of the scalar gradients over the sweep
     // (each workgroup adds its steps in order; one fixed-order reduction at the end)
-    ADJ_TRY(hipMemsetAsync(A->part, 0, sizeof(double) * nb_node * NV, s));
+    ADJ_TRY(hipMemsetAsync(A->part, 0, sizeof(double) * nb_node * (NV + d), s));
     ADJ_TRY(hipMemsetAsync(A->part2, 0, sizeof(double) * nb * d, s));
     hipLaunchKernelGGL(broadcast_kernel, dim3(nblk(nodes)), dim3(kBlock), 0, s, gC, A->fbar, Q, nodes);
     ADJ_TRY(hipGetLastError());
-    const int offU = d * d, offTr = d * d + d, offP = d * d + d + 1;
+    const int offU = d * d, offTr = d * d + d, offP = NV;
     // Segment sg recomputed into buffer b from its checkpoint: populations, C
     // and Phi of each of its steps.
     auto seg_len = [&](int64_t sg) { return (int)((sg * K + K <= n ? sg * K + K : n) - sg * K); };
@@ -674,6 +726,9 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
         ADJ_TRY(hipEventRecord(A->ev_rec[(nseg - 1) % 2], A->side));
     }
     bool swept[2] = {false, false};
+    float* fdirB[2] = {A->fdir, A->fdir2};
+    float* cbarB[2] = {A->cbar, A->cbar2};
+    float* phibarB[2] = {A->phibar, A->phibar2};
     for (int64_t sg = nseg - 1; sg >= 0; --sg) {
         const int len = seg_len(sg);
         const int b = overlap ? (int)(sg % 2) : 0;
@@ -691,32 +746,52 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
             if (rc) return rc;
         }
         for (int j = len - 1; j >= 0; --j) {
+            const int64_t t = sg * K + j;
             const float* phi_j = A->seg_phi[b] + (int64_t)j * d * nodes;
-            const float* C_j = A->seg_C[b] + (int64_t)j * nodes;
-            if (Q == 5)
-                hipLaunchKernelGGL(adjoint_node<5>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_of(sg, b, j), phi_j,
-                                   A->fdir, A->cbar, A->phibar, A->dS, A->part, nodes);
-            else
-                hipLaunchKernelGGL(adjoint_node<7>, node_grid, dim3(kBlock), 0, s, ac, A->fbar, f_of(sg, b, j), phi_j,
-                                   A->fdir, A->cbar, A->phibar, A->dS, A->part, nodes);
+            float* fdir_t = fdirB[t & 1];
+            float* cbar_t = cbarB[t & 1];
+            float* phibar_t = phibarB[t & 1];
+            // step t + 1's fields; its C is in this segment's buffer, or (for
+            // the segment's last step) in the copy kept from the segment swept before
+            LaterStep ls;
+            ls.fbar = A->fbar;
+            ls.fdir = fdirB[(t + 1) & 1];
+            ls.cbar = cbarB[(t + 1) & 1];
+            ls.phibar = phibarB[(t + 1) & 1];
+            ls.tu = A->tu;
+            ls.tl = A->tl;
+            ls.C = j + 1 < len ? A->seg_C[b] + (int64_t)(j + 1) * nodes : A->Ckeep;
+            const bool first = t == n - 1;  // fbar^n is the broadcast of gC
+            auto node_kern = Q == 5 ? (first ? adjoint_node<5, false> : adjoint_node<5, true>)
+                                    : (first ? adjoint_node<7, false> : adjoint_node<7, true>);
+            hipLaunchKernelGGL(node_kern, node_grid, dim3(kBlock), 0, s, ac, A->rc, ls, f_of(sg, b, j), phi_j, fdir_t,
+                               cbar_t, phibar_t, A->dS, A->part, nodes);
             ADJ_TRY(hipGetLastError());
-            // fractional term reversed: K^T Phibar and <Phibar, (dK/dp) C> from
-            // the two triangular products of Phibar
-            ADJ_TRY(reversed_phi());
-            if (d == 2)
-                hipLaunchKernelGGL(combine_dot<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, A->fdir, A->cbar,
-                                   A->tu, A->tl, A->phibar, C_j, A->fbar, Q, A->part2, nodes);
-            else
-                hipLaunchKernelGGL(combine_dot<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, A->fdir, A->cbar,
-                                   A->tu, A->tl, A->phibar, C_j, A->fbar, Q, A->part2, nodes);
-            ADJ_TRY(hipGetLastError());
+            // fractional term reversed: the two triangular products of Phibar,
+            // read by the next kernel (K^T Phibar and <Phibar, (dK/dp) C>)
+            ADJ_TRY(reversed_phi(phibar_t));
         }
+        // the next segment's sweep starts with a step whose later step is this
+        // segment's first; its buffer is recomputed before that sweep ends
+        if (sg > 0) ADJ_TRY(hipMemcpyAsync(A->Ckeep, A->seg_C[b], sizeof(float) * nodes, hipMemcpyDeviceToDevice, s));
         if (overlap) {
             ADJ_TRY(hipEventRecord(A->ev_rev[b], s));
             swept[b] = true;
         }
     }
-    hipLaunchKernelGGL(reduce_partials, dim3(NV), dim3(kBlock), 0, s, A->part, nb_node, NV, A->acc, 0);
+    // fbar^0 = fdir^0 + Cbar^0 + sum_mu K_mu^T Phibar^0_mu and step 0's p-gradient terms
+    // (C^0 is slot 0 of buffer 0, which segment 0 was recomputed into)
+    if (n > 0) {
+        if (d == 2)
+            hipLaunchKernelGGL(combine_dot<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, fdirB[0], cbarB[0], A->tu,
+                               A->tl, phibarB[0], A->seg_C[0], A->fbar, Q, A->part2, nodes);
+        else
+            hipLaunchKernelGGL(combine_dot<3>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, fdirB[0], cbarB[0], A->tu,
+                               A->tl, phibarB[0], A->seg_C[0], A->fbar, Q, A->part2, nodes);
+        ADJ_TRY(hipGetLastError());
+    }
+    // slots NV .. NV + d of the node partials are the p-gradient (offP == NV)
+    hipLaunchKernelGGL(reduce_partials, dim3(NV + d), dim3(kBlock), 0, s, A->part, nb_node, NV + d, A->acc, 0);
     ADJ_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part2, nb, d, A->acc, offP);
     ADJ_TRY(hipGetLastError());
@@ -732,7 +807,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     ADJ_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials, dim3(d), dim3(kBlock), 0, s, A->part, nb, d, A->acc, offU);
     ADJ_TRY(hipGetLastError());
-    ADJ_TRY(reversed_phi());
+    ADJ_TRY(reversed_phi(A->phibar));
     float* dC0dst = dC0 ? (on_device ? dC0 : A->fdir) : nullptr;  // fdir: scratch for a host destination
     if (d == 2)
         hipLaunchKernelGGL(combine_init<2>, dim3(nblk(nodes)), dim3(kBlock), 0, s, A->rc, A->cbar, A->tu, A->tl,
