@@ -671,27 +671,6 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
         ADJ_TRY(hipMemcpyAsync(gCdev, gC, sizeof(float) * nodes, hipMemcpyHostToDevice, s));
         gC = gCdev;
     }
-    // --- forward pass with checkpoints (the handle's state advances to step n)
-    for (int64_t t = 0; t < n; ++t) {
-        if (t % K == 0) ADJ_TRY(hipMemcpyAsync(A->ckpt + (t / K) * Q * nodes, h->f[h->cur], fq,
-                                               hipMemcpyDeviceToDevice, s));
-        int rc = fade_forward_step(h, s);
-        if (rc) {
-            msg = "forward step failed";
-            return rc;
-        }
-    }
-    if (n == 0) ADJ_TRY(hipMemcpyAsync(A->ckpt, h->f[h->cur], fq, hipMemcpyDeviceToDevice, s));
-    // --- reverse sweep
-    ADJ_TRY(hipMemsetAsync(A->acc, 0, sizeof(double) * 64, s));
-    ADJ_TRY(hipMemsetAsync(A->dS, 0, sizeof(float) * nodes, s));
-    // per-workgroup running sums of the scalar gradients over the sweep
-    // (each workgroup adds its steps in order; one fixed-order reduction at the end)
-    ADJ_TRY(hipMemsetAsync(A->part, 0, sizeof(double) * nb_node * (NV + d), s));
-    ADJ_TRY(hipMemsetAsync(A->part2, 0, sizeof(double) * nb * d, s));
-    hipLaunchKernelGGL(broadcast_kernel, dim3(nblk(nodes)), dim3(kBlock), 0, s, gC, A->fbar, Q, nodes);
-    ADJ_TRY(hipGetLastError());
-    const int offU = d * d, offTr = d * d + d, offP = NV;
     // Segment sg recomputed into buffer b from its checkpoint: populations, C
     // and Phi of each of its steps.
     auto seg_len = [&](int64_t sg) { return (int)((sg * K + K <= n ? sg * K + K : n) - sg * K); };
@@ -718,12 +697,51 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     // while segment sg is swept on s; events order each buffer's reuse.
     const char* ov = getenv("LBM_ADJOINT_OVERLAP");  // "0": one buffer, in order (measurement and tests)
     const bool overlap = A->nbuf == 2 && nseg > 1 && !(ov && ov[0] == '0');
+    auto buf_of = [&](int64_t sg) { return overlap ? (int)(sg % 2) : 0; };
+
+    // --- forward pass with checkpoints (the handle's state advances to step n).
+    // The last segment runs as its own recompute, into the buffer the reverse
+    // sweep reads first, and its last step from there: the same kernels on the
+    // same inputs as the plain step (the moment kernel and the collide-stream
+    // kernel sum C in the same order), so the state is the same.
+    const int64_t t_last = (nseg - 1) * K;  // first step of the last segment
+    for (int64_t t = 0; t < n; ++t) {
+        if (t % K == 0) ADJ_TRY(hipMemcpyAsync(A->ckpt + (t / K) * Q * nodes, h->f[h->cur], fq,
+                                               hipMemcpyDeviceToDevice, s));
+        if (t == t_last) break;
+        int rc = fade_forward_step(h, s);
+        if (rc) {
+            msg = "forward step failed";
+            return rc;
+        }
+    }
+    if (n == 0) ADJ_TRY(hipMemcpyAsync(A->ckpt, h->f[h->cur], fq, hipMemcpyDeviceToDevice, s));
+    if (n > 0) {
+        const int64_t sg = nseg - 1;
+        const int b = buf_of(sg), len = seg_len(sg);
+        int rc = recompute(sg, b, s);
+        if (rc) return rc;
+        ADJ_TRY(launch_collide_stream(h->cc, f_of(sg, b, len - 1), h->f[1 - h->cur],
+                                      A->seg_phi[b] + (int64_t)(len - 1) * d * nodes, h->S, h->C, h->Cp, s));
+        h->cur = 1 - h->cur;
+        h->steps_done += len;
+        h->at_initial_C = false;
+    }
+    // --- reverse sweep
+    ADJ_TRY(hipMemsetAsync(A->acc, 0, sizeof(double) * 64, s));
+    ADJ_TRY(hipMemsetAsync(A->dS, 0, sizeof(float) * nodes, s));
+    // per-workgroup running sums of the scalar gradients over the sweep
+    // (each workgroup adds its steps in order; one fixed-order reduction at the end)
+    ADJ_TRY(hipMemsetAsync(A->part, 0, sizeof(double) * nb_node * (NV + d), s));
+    ADJ_TRY(hipMemsetAsync(A->part2, 0, sizeof(double) * nb * d, s));
+    hipLaunchKernelGGL(broadcast_kernel, dim3(nblk(nodes)), dim3(kBlock), 0, s, gC, A->fbar, Q, nodes);
+    ADJ_TRY(hipGetLastError());
+    const int offU = d * d, offTr = d * d + d, offP = NV;
     if (overlap) {
+        // the side stream's first recompute (segment nseg - 2) reads checkpoints
+        // written above
         ADJ_TRY(hipEventRecord(A->ev_fwd, s));
         ADJ_TRY(hipStreamWaitEvent(A->side, A->ev_fwd, 0));
-        int rc = recompute(nseg - 1, (int)((nseg - 1) % 2), A->side);
-        if (rc) return rc;
-        ADJ_TRY(hipEventRecord(A->ev_rec[(nseg - 1) % 2], A->side));
     }
     bool swept[2] = {false, false};
     float* fdirB[2] = {A->fdir, A->fdir2};
@@ -731,9 +749,10 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
     float* phibarB[2] = {A->phibar, A->phibar2};
     for (int64_t sg = nseg - 1; sg >= 0; --sg) {
         const int len = seg_len(sg);
-        const int b = overlap ? (int)(sg % 2) : 0;
+        const int b = buf_of(sg);
+        const bool ready = sg == nseg - 1;  // computed by the forward pass
         if (overlap) {
-            ADJ_TRY(hipStreamWaitEvent(s, A->ev_rec[b], 0));
+            if (!ready) ADJ_TRY(hipStreamWaitEvent(s, A->ev_rec[b], 0));
             if (sg >= 1) {
                 const int nb2 = 1 - b;
                 if (swept[nb2]) ADJ_TRY(hipStreamWaitEvent(A->side, A->ev_rev[nb2], 0));
@@ -741,7 +760,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
                 if (rc) return rc;
                 ADJ_TRY(hipEventRecord(A->ev_rec[nb2], A->side));
             }
-        } else {
+        } else if (!ready) {
             int rc = recompute(sg, 0, s);
             if (rc) return rc;
         }

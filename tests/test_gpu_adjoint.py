@@ -108,6 +108,36 @@ def test_segment_overlap_does_not_change_gradients(dim, n, precision, monkeypatc
         assert np.array_equal(g1[key], g0[key])
 
 
+@pytest.mark.parametrize("dim,n,precision,steps,K", [(2, [45, 38], "fp32", 17, 4), (2, [40, 33], "bf16x3", 12, 4),
+                                                    (3, [21, 17, 12], "fp32", 9, 9), (3, [19, 14, 11], "bf16x3", 7, 3)])
+@pytest.mark.parametrize("ov", ["1", "0"])
+def test_state_after_adjoint_is_the_forward_state(dim, n, precision, steps, K, ov, monkeypatch):
+    """The adjoint's forward pass (its last segment run as that segment's
+    recompute) leaves the handle in the state of `steps` plain steps, bit for
+    bit, and later steps continue from it as from the plain steps."""
+    print(f"[gpu-adjoint-state] dim={dim} n={n} {precision} steps={steps} K={K} overlap={ov}", flush=True)
+    monkeypatch.setenv("LBM_ADJOINT_OVERLAP", ov)
+    cfg = synth.small(dim, n, seed=85, with_source=True, c_wall=0.1)
+    C0 = synth.initial_C(cfg).astype(np.float32)
+    S = synth.source(cfg).astype(np.float32)
+    gC = np.random.default_rng(9).standard_normal(synth.shape(cfg)).astype(np.float32)
+    with _solver(cfg, precision) as s:
+        s.set_C(C0)
+        s.set_source(S)
+        s.step(steps)
+        f_ref, C_ref = s.get_f(device=False).copy(), s.get_C(device=False).copy()
+        s.step(3)
+        f_ref3 = s.get_f(device=False).copy()
+    with _solver(cfg, precision) as s:
+        s.set_C(C0)
+        s.set_source(S)
+        s.adjoint(steps, K, gC, want_fields=False)
+        assert np.array_equal(s.get_f(device=False).view(np.uint32), f_ref.view(np.uint32))
+        assert np.array_equal(s.get_C(device=False).view(np.uint32), C_ref.view(np.uint32))
+        s.step(3)
+        assert np.array_equal(s.get_f(device=False).view(np.uint32), f_ref3.view(np.uint32))
+
+
 def test_linear_identity_on_gpu():
     """Zero wall value: <gC, C_n> = <dL/dC0, C0> + <dL/dS, S> for the GPU's own forward and adjoint."""
     cfg = synth.small(2, [50, 44], seed=83, with_source=True)
