@@ -199,7 +199,8 @@ typedef struct {
  * the first call: ceil(n / ckpt_every) checkpoints of the populations, and two
  * segment buffers of ckpt_every steps (populations, C and the fractional
  * terms) when both fit (one otherwise: the recompute then no longer overlaps
- * the reverse sweep on the handle's internal second stream).  The solver state
+ * the reverse sweep on the handle's internal second stream), and the reverse
+ * sweep's work fields (3Q + 4d + 4 floats per node).  The solver state
  * after the call is the state after n steps.  Synchronises `stream` (the
  * scalar gradients are written to host memory). */
 LBM_API int lbm_fade_adjoint(lbm_fade_t h, int64_t n, int32_t ckpt_every, const float* gC, int32_t on_device,
