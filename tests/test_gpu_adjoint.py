@@ -67,6 +67,40 @@ def test_adjoint_matches_oracle(dim, n, collision, c_wall, steps, K, flux_form):
         assert np.abs(g[key] - ref[key]).max() <= 1e-5 * scale, (key, g[key], ref[key])
 
 
+@pytest.mark.parametrize("dim,n,steps,K", [(2, [23, 19], 0, 1), (2, [23, 19], 1, 1), (2, [23, 19], 1, 4),
+                                          (2, [23, 19], 2, 1), (3, [11, 9, 8], 0, 3), (3, [11, 9, 8], 1, 3)])
+def test_adjoint_of_zero_one_and_two_steps(dim, n, steps, K):
+    """The shortest sweeps: no reversed step (the gradients of <gC, C_0>:
+    dC0 = gC off the walls, dS, dD and du exactly zero; dp is zero up to the
+    FP32 rounding of Phibar = (2 w - w0) gC, formed with a fused multiply-add,
+    so it is held to 1e-5 of the one-step gradients), one (its own first and
+    last step), two (one step read from the broadcast, one fused)."""
+    print(f"[gpu-adjoint-short] dim={dim} n={n} steps={steps} K={K}", flush=True)
+    cfg = synth.small(dim, n, seed=86, with_source=True, c_wall=0.2)
+    C0 = synth.initial_C(cfg).astype(np.float32)
+    S = synth.source(cfg).astype(np.float32)
+    gC = np.random.default_rng(10).standard_normal(synth.shape(cfg)).astype(np.float32)
+    ref = oracle.adjoint(cfg, C0.astype(np.float64), steps, gC.astype(np.float64), S=S.astype(np.float64))
+    with _solver(cfg) as s:
+        s.set_C(C0)
+        s.set_source(S)
+        g, dC0, dS = s.adjoint(steps, K, gC)
+    assert _rel(dC0, ref["dC0"]) < 1e-5
+    if steps == 0:
+        assert not np.any(dS)
+        for key in ("D", "u"):
+            assert not np.any(g[key]) and not np.any(ref[key]), (key, g[key], ref[key])
+        assert not np.any(ref["p"])
+        ref1 = oracle.adjoint(cfg, C0.astype(np.float64), 1, gC.astype(np.float64), S=S.astype(np.float64))
+        scale1 = max(np.abs(ref1["D"]).max(), np.abs(ref1["u"]).max(), np.abs(ref1["p"]).max())
+        assert np.abs(g["p"]).max() <= 1e-5 * scale1, (g["p"], scale1)
+        return
+    assert _rel(dS, ref["dS"]) < 1e-5
+    scale = max(np.abs(ref["D"]).max(), np.abs(ref["u"]).max(), np.abs(ref["p"]).max())
+    for key in ("D", "u", "p"):
+        assert np.abs(g[key] - ref[key]).max() <= 1e-5 * scale, (key, g[key], ref[key])
+
+
 def test_checkpoint_interval_does_not_change_gradients():
     cfg = synth.small(2, [40, 31], seed=82, with_source=True)
     C0 = synth.initial_C(cfg).astype(np.float32)
