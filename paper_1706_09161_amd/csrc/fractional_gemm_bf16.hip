@@ -843,7 +843,8 @@ hipError_t launch_fractional_bf16x3(FracLaunch& L, hipStream_t s)
     // with k split 4 ways.  Measured on MI355X (kernel trace, us, against the
     // other choice): 64^3 8.9 (11.1), 96^3 14.5 (19.9), 128^3 21.2 (30.6),
     // 320^3 406 (491), 384^3 579 (664); 256^3 128 (142); 2D 512^2 9.0 (11.3),
-    // 1024^2, 1536^2 51.0 (53.3).
+    // 1536^2 51.0 (53.3).  At 1024^2 (timed per launch) 15.7-16.8 us against
+    // 16.7-36.3 for the other ring tiles of the table.
     {
         bool batched = false, whole = true;
         for (int a = 0; a < L.naxes; ++a) {
