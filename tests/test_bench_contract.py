@@ -30,3 +30,27 @@ def test_counter_summary_matches_the_gemm_sources():
     assert traffic is not None, "profiles/gemm_fp32__2d_1024sq_pmc.txt was taken from other GEMM sources"
     # FETCH + WRITE per launch: within a few percent of the algorithmic 16 MiB
     assert 0.95 * 16777216 <= traffic <= 1.5 * 16777216
+
+
+def test_profile_commands_use_existing_options_and_workloads():
+    """Every bench.py command recorded in profiles/ names options bench.py
+    accepts and workloads the synthetic-input module defines, so each summary
+    can be taken again from the committed files."""
+    import re
+
+    import synth
+
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    prof = os.path.join(ROOT, "profiles")
+    seen = 0
+    for name in sorted(os.listdir(prof)):
+        text = open(os.path.join(prof, name)).read()
+        for m in re.finditer(r"python3? bench\.py((?: --?[\w-]+(?: [\w.]+)?)*)", text):
+            args = m.group(1).split()
+            seen += 1
+            for i, a in enumerate(args):
+                if a.startswith("--"):
+                    assert f'"{a}"' in src, (name, a)
+                    if a == "--profile-workload":
+                        synth.config(args[i + 1])
+    assert seen >= 5
