@@ -198,13 +198,17 @@ typedef struct {
     double* cm; /* (N+1)^2, cm[n*(N+1) + l] = c-_{ln} */
 } coeff_table;
 
-static int make_table(int64_t N, double gamma, coeff_table* T)
+/* A one-sided operator (p = 1 or p = 0) weighs one of the two integrals by
+ * exactly zero: the forward term then builds no table for that integral and
+ * forms no sum with it (for finite C, adding 0 * sum changes no value).  The
+ * adjoint needs both tables for the p-derivative. */
+static int make_table(int64_t N, double gamma, int need_plus, int need_minus, coeff_table* T)
 {
     const int64_t m = N + 1;
     T->N = N;
-    T->cp = (double*)malloc(sizeof(double) * m * m);
-    T->cm = (double*)malloc(sizeof(double) * m * m);
-    if (!T->cp || !T->cm) {
+    T->cp = need_plus ? (double*)malloc(sizeof(double) * m * m) : NULL;
+    T->cm = need_minus ? (double*)malloc(sizeof(double) * m * m) : NULL;
+    if ((need_plus && !T->cp) || (need_minus && !T->cm)) {
         free(T->cp);
         free(T->cm);
         return FO_ENOMEM;
@@ -212,8 +216,8 @@ static int make_table(int64_t N, double gamma, coeff_table* T)
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < m; ++n)
         for (int64_t l = 0; l < m; ++l) {
-            T->cp[n * m + l] = fo_cplus(l, n, gamma);
-            T->cm[n * m + l] = fo_cminus(l, n, N, gamma);
+            if (T->cp) T->cp[n * m + l] = fo_cplus(l, n, gamma);
+            if (T->cm) T->cm[n * m + l] = fo_cminus(l, n, N, gamma);
         }
     return FO_OK;
 }
@@ -231,8 +235,10 @@ static double phi_on_line(const coeff_table* T, const double* line, int64_t n,
 {
     const int64_t m = T->N + 1;
     double splus = 0.0, sminus = 0.0;
-    for (int64_t l = 0; l <= n; ++l) splus += T->cp[n * m + l] * (g * line[l]);
-    for (int64_t l = n; l <= T->N; ++l) sminus += T->cm[n * m + l] * (g * line[l]);
+    if (T->cp)
+        for (int64_t l = 0; l <= n; ++l) splus += T->cp[n * m + l] * (g * line[l]);
+    if (T->cm)
+        for (int64_t l = n; l <= T->N; ++l) sminus += T->cm[n * m + l] * (g * line[l]);
     return p * (pref * splus) + (1.0 - p) * (pref * sminus);
 }
 
@@ -263,7 +269,7 @@ int fo_phi(const fo_problem* P, const double* C, double* Phi)
         const double gamma = 2.0 - P->alpha[mu];
         const double pref = pow(P->dx, gamma) / tgamma(2.0 + gamma);
         coeff_table T;
-        if (make_table(N, gamma, &T)) return FO_ENOMEM;
+        if (make_table(N, gamma, P->p[mu] != 0.0, P->p[mu] != 1.0, &T)) return FO_ENOMEM;
         double* out = Phi + (int64_t)mu * nodes;
         int failed = 0;
 #pragma omp parallel
@@ -879,7 +885,7 @@ static int axis_prepare(const fo_problem* P, int mu, axis_data* A)
     A->alpha = P->alpha[mu];
     A->dx = P->dx;
     A->flux_form = P->flux_form;
-    return make_table(A->len - 1, gamma, &A->T);
+    return make_table(A->len - 1, gamma, 1, 1, &A->T);
 }
 
 /* Adjoint of Phi_mu = K_mu C along every line of axis mu: Cbar += K^T Phibar,
