@@ -479,6 +479,65 @@ def test_d4_symmetry_of_symmetric_workload(oracle_lib):
     assert np.allclose(C, C[:, ::-1], atol=1e-14)
 
 
+def _symmetries(dim):
+    """The box's symmetries as (map of a field, map of a population index):
+    axis swaps and reflections of a field stored slowest axis first, with
+    populations ordered 0, +x, -x, +y, -y (, +z, -z)."""
+    out = []
+    Q = 2 * dim + 1
+    for a in range(dim):
+        for b in range(a + 1, dim):  # swap axes a and b (array dims dim-1-a, dim-1-b)
+            perm = list(range(Q))
+            for s_ in (0, 1):
+                perm[2 * a + 1 + s_], perm[2 * b + 1 + s_] = 2 * b + 1 + s_, 2 * a + 1 + s_
+            out.append((lambda F, a=a, b=b: np.swapaxes(F, dim - 1 - a, dim - 1 - b), perm))
+        perm = list(range(Q))  # reflect axis a
+        perm[2 * a + 1], perm[2 * a + 2] = 2 * a + 2, 2 * a + 1
+        out.append((lambda F, a=a: np.flip(F, axis=dim - 1 - a), perm))
+    return out
+
+
+@pytest.mark.parametrize("dim,n", [(2, 14), (3, 10)])
+def test_box_symmetry_pins_corner_and_edge_shares(oracle_lib, dim, n):
+    """Equal orders, p = 1/2, isotropic D, u = 0, a pulse centred in the box
+    and a non-zero wall value: the populations keep the box's symmetries,
+    f_i(x) = f_sigma(i)(sigma x) for every axis swap and reflection sigma.  At
+    a 2D corner or 3D edge node a reflection exchanges the two unknown
+    populations, and at a 3D corner the axis swaps permute the three, so
+    only the equal 2-way and 3-way shares of the Dirichlet deficit (the
+    reading used for Sec. 2.5's single-unknown rule) keep this symmetry.
+    (C alone cannot pin the split: a zero-sum change of the unknown
+    populations at a corner or edge leaves C unchanged at every node; the
+    populations it changes only reach interior nodes in zero-mass pairs.)"""
+    c = (n - 1) / 2.0
+    iso = (0.1 * np.eye(dim)).tolist()
+    cfg = synth.small(dim, [n] * dim, seed=27, alpha=[1.5] * dim, p=[0.5] * dim, u=[0.0] * dim, D=iso,
+                      c_wall=0.3)
+    X = np.meshgrid(*(np.arange(n, dtype=np.float64),) * dim, indexing="ij")
+    C0 = np.exp(-sum((x - c) ** 2 for x in X) / (2 * 2.0 ** 2))
+    f = oracle_lib.init(cfg, C0)
+    f = oracle_lib.step(cfg, f, 30)
+    scale = np.abs(f).max()
+    for fmap, perm in _symmetries(dim):
+        g = np.stack([fmap(f[i]) for i in range(2 * dim + 1)])
+        assert np.abs(g[perm] - f).max() <= 1e-13 * scale, perm
+    corner = (0,) * dim
+    unknown = [f[2 * mu + 1][corner] for mu in range(dim)]  # +x, +y (, +z) come from outside
+    assert np.ptp(unknown) <= 1e-13 * scale and abs(unknown[0]) > 1e-3 * scale
+
+
+def test_one_sided_operator_skips_the_zero_weighted_integral(oracle_lib):
+    """p = 1 or p = 0 weighs one integral by exactly zero: the full-field
+    term, which then forms only the other sum, equals the node-by-node term,
+    which forms both, bit for bit."""
+    cfg = synth.small(2, [19, 23], seed=28, alpha=[1.3, 1.8], p=[1.0, 0.0])
+    C = np.random.default_rng(3).uniform(-1, 1, (23, 19))
+    full = oracle_lib.phi(cfg, C)
+    nodes = np.arange(19 * 23)
+    at = oracle_lib.phi_at(cfg, C, nodes)
+    assert np.array_equal(full.reshape(2, -1), at.reshape(2, -1))
+
+
 def test_mirror_p_and_u(oracle_lib):
     """Mirroring x maps p_x -> 1 - p_x and u_x -> -u_x (D diagonal)."""
     cfg = synth.small(2, [21, 17], seed=22, alpha=[1.4, 1.7], p=[0.2, 0.65], u=[0.03, 0.01],
