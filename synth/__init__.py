@@ -201,6 +201,17 @@ class PowerLawProblem:
     def source(self, t: float) -> np.ndarray:
         return -math.exp(-t) * ((self.dim + 1) * self.base + self.extra)
 
+    def schedule32(self, m: int):
+        """The FP32 fields an FP32 run receives before step m: the source at
+        t_m and the wall values at t_{m+1} (t = m dt), each formed in FP32
+        from the FP32-rounded base fields and time factors.  Giving these to
+        both sides keeps input rounding out of a parity comparison."""
+        dt = self.cfg["dt"]
+        e0, e1 = np.float32(math.exp(-m * dt)), np.float32(math.exp(-(m + 1) * dt))
+        b, x = self.base.astype(np.float32), self.extra.astype(np.float32)
+        S = np.float32(-(self.dim + 1)) * e0 * b - e0 * x
+        return S.astype(np.float32), (e1 * b).astype(np.float32)
+
 
 def random_tensor_field(cfg: dict, seed: int, zero_fraction: float = 0.05) -> np.ndarray:
     """Seeded field of symmetric positive semi-definite d x d tensors, shape
@@ -272,6 +283,15 @@ class CaputoPowerLawProblem:
 
     def source(self, t: float) -> np.ndarray:
         return -math.exp(-t) * (self.base + self.flux_div)
+
+    def schedule32(self, m: int):
+        """The FP32 source (t_m) and wall values (t_{m+1}) an FP32 run receives
+        before step m, formed in FP32 from the FP32-rounded base fields."""
+        dt = self.cfg["dt"]
+        e0, e1 = np.float32(math.exp(-m * dt)), np.float32(math.exp(-(m + 1) * dt))
+        b, fl = self.base.astype(np.float32), self.flux_div.astype(np.float32)
+        S = -(e0 * (b + fl))
+        return S.astype(np.float32), (e1 * b).astype(np.float32)
 
 
 # ---------------------------------------------------------------------------

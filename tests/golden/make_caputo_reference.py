@@ -2,8 +2,9 @@
 variant (Sec. 3.5) at the paper's setting: 2D, alpha = (1.7, 1.2),
 a = (0.3, 1.2), p = 1, D = Id, g = 1, u = 0, dx = 0.02 on [0, 1]^2 (51 nodes
 per axis), dt = 2.5e-5, MRT, source (SourceTerm_PS) at t_m and wall values
-C(t_{m+1}) set before every step m.  Stores C at t = 0.025 and 0.425 (steps
-1000 and 17000) in FP64.  Calls only ``oracle`` and ``synth``.
+C(t_{m+1}) set before every step m, in the FP32 values an FP32 run gets
+(synth.CaputoPowerLawProblem.schedule32).  Stores C at t = 0.025 and 0.425
+(steps 1000 and 17000) in FP64.  Calls only ``oracle`` and ``synth``.
 
     python tests/golden/make_caputo_reference.py
 """
@@ -26,11 +27,13 @@ MARKS = (1000, 17000)
 
 def make() -> str:
     P = synth.CaputoPowerLawProblem(2, 51, DT)
-    f = oracle.init(P.cfg, P.base, Cw=P.exact(0.0))
+    base = P.base.astype(np.float32).astype(np.float64)
+    f = oracle.init(P.cfg, base, Cw=base)
     out = {}
     t = time.time()
     for m in range(MARKS[-1]):
-        f = oracle.step(P.cfg, f, 1, S=P.source(m * DT), Cw=P.exact((m + 1) * DT))
+        S, Cw = P.schedule32(m)
+        f = oracle.step(P.cfg, f, 1, S=S.astype(np.float64), Cw=Cw.astype(np.float64))
         if m + 1 in MARKS:
             out[f"C{m + 1}"] = oracle.moment(P.cfg, f)
     np.savez_compressed(PATH, steps=np.array(MARKS), dt=DT, seconds=time.time() - t, **out)
