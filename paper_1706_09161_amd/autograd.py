@@ -6,7 +6,14 @@ checkpoint-and-recompute.
     loss = 0.5 * ((C_n - C_obs) ** 2).sum()
     loss.backward()      # gradients for C0, S, D, u, p
 
-D, u, p are small tensors (any device); C0 and S are node fields on the GPU.
+D (d x d, symmetric), u and p (d values each) are small tensors on any
+device; C0 and S (S may be None) are node fields on the GPU, slowest axis
+first.  C_n is float32 (the step computes in FP32).  Each gradient has the
+dtype and device of its input; D's gradient is the symmetrised one (a
+symmetric perturbation dD changes the loss by sum_ab grad_ab dD_ab), so a D
+built from tied off-diagonal parameters receives their full derivative.
+Every other keyword (g, dx, dt, tau_free, tau0, c_wall, collision,
+precision, flux_form, nonfinite_check_every) goes to the solver unchanged.
 Every call creates a solver for the given parameters (they are create-time
 constants of the library), so keep one call per optimisation step.
 """
@@ -28,42 +35,52 @@ class FadeSolve(torch.autograd.Function):
         dim = C0.dim()
         n = list(reversed(C0.shape))
         Dm = np.array(_vals(D)).reshape(dim, dim)
-        solver = LbmFade(dim, n, alpha=opts["alpha"], p=_vals(p), D=Dm, u=_vals(u), g=opts.get("g"),
-                         dx=opts.get("dx", 1.0), dt=opts.get("dt", 1.0), tau_free=opts.get("tau_free"),
-                         tau0=opts.get("tau0", 1.0), c_wall=opts.get("c_wall", 0.0),
-                         collision=opts.get("collision", "MRT"), precision=opts.get("precision", "fp32"))
-        C0c = C0.detach().float().contiguous()
-        Sc = None if S is None else S.detach().float().contiguous()
-        solver.set_C(C0c)
-        solver.set_source(Sc)
-        solver.step(opts["steps"])
-        out = solver.get_C()
+        kw = {k: v for k, v in opts.items() if k not in ("alpha", "steps", "ckpt_every")}
+        solver = LbmFade(dim, n, alpha=opts["alpha"], p=_vals(p), D=Dm, u=_vals(u), **kw)
+        try:
+            solver.set_C(C0.detach().float().contiguous())
+            solver.set_source(None if S is None else S.detach().float().contiguous())
+            solver.step(opts["steps"])
+            out = solver.get_C()
+        except Exception:
+            solver.close()
+            raise
+        # the inputs themselves are saved, so an in-place change before
+        # backward() is caught by autograd's version check
+        ctx.save_for_backward(C0, S, D, u, p)
         ctx.solver = solver
-        ctx.saved = (C0c, Sc)
         ctx.opts = opts
-        ctx.meta = (D, u, p, S is not None)
         return out
 
     @staticmethod
     def backward(ctx, gC):
-        solver, (C0c, Sc), opts = ctx.solver, ctx.saved, ctx.opts
-        D, u, p, has_S = ctx.meta
-        solver.set_C(C0c)
-        solver.set_source(Sc)
-        grads, dC0, dS = solver.adjoint(opts["steps"], opts.get("ckpt_every", 50), gC.detach().float().contiguous())
-        solver.close()
+        C0, S, D, u, p = ctx.saved_tensors
+        solver, opts = ctx.solver, ctx.opts
         ctx.solver = None
+        try:
+            solver.set_C(C0.detach().float().contiguous())
+            solver.set_source(None if S is None else S.detach().float().contiguous())
+            grads, dC0, dS = solver.adjoint(opts["steps"], opts.get("ckpt_every", 50),
+                                            gC.detach().float().contiguous())
+        finally:
+            solver.close()
 
         def like(val, ref):
             t = torch.as_tensor(np.asarray(val, dtype=np.float64))
-            r = torch.as_tensor(ref)
-            return t.reshape(r.shape).to(dtype=r.dtype if r.is_floating_point() else torch.float64, device=r.device)
+            return t.reshape(ref.shape).to(dtype=ref.dtype, device=ref.device)
 
-        return (dC0, dS if has_S else None, like(grads["D"], D), like(grads["u"], u), like(grads["p"], p), None)
+        need = ctx.needs_input_grad
+        return (dC0.to(C0.dtype) if need[0] else None,
+                dS.to(S.dtype) if (S is not None and need[1]) else None,
+                like(grads["D"], D) if need[2] else None,
+                like(grads["u"], u) if need[3] else None,
+                like(grads["p"], p) if need[4] else None,
+                None)
 
 
 def fade_solve(C0, S, D, u, p, *, alpha, steps: int, ckpt_every: int = 50, **opts):
     """C after `steps` time steps, differentiable in C0, S, D, u and p."""
     o = dict(opts)
     o.update(alpha=list(alpha), steps=int(steps), ckpt_every=int(ckpt_every))
+    D, u, p = (torch.as_tensor(x, dtype=torch.float64) if not isinstance(x, torch.Tensor) else x for x in (D, u, p))
     return FadeSolve.apply(C0, S, D, u, p, o)

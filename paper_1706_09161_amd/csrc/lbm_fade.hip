@@ -419,6 +419,7 @@ int build_step_graph(lbm_fade* h)
     h->gcur = cur0;
     h->gS = h->S;
     h->gdB = h->cc.dB;
+    h->gCw = h->cc.Cw;
     graph_key(h->gkey);
     return LBM_OK;
 }
@@ -458,6 +459,7 @@ int release_var_fields(lbm_fade* h, hipStream_t s)
 {
     if (h->var_D || h->var_wall || !h->dB) return LBM_OK;
     HIP_TRY(hipStreamSynchronize(s));
+    drop_graph(h);  // a captured graph reads these fields
     (void)hipFree(h->dB);
     (void)hipFree(h->Cw);
     h->dB = h->Cw = nullptr;
@@ -835,7 +837,8 @@ int lbm_fade_step(lbm_fade_t h, int64_t n, void* stream)
     if (every == 0 && n >= kGraphSteps && graphs_enabled()) {
         int key[4];
         graph_key(key);
-        if (!h->gexec || h->gS != h->S || h->gdB != h->cc.dB || key[0] != h->gkey[0] || key[1] != h->gkey[1] ||
+        if (!h->gexec || h->gS != h->S || h->gdB != h->cc.dB || h->gCw != h->cc.Cw || key[0] != h->gkey[0] ||
+            key[1] != h->gkey[1] ||
             key[2] != h->gkey[2] || key[3] != h->gkey[3]) {
             rc = build_step_graph(h);
             if (rc) return rc;

@@ -49,7 +49,8 @@ struct lbm_fade {
     hipGraphExec_t gexec = nullptr;
     int gcur = 0;                   // f[gcur] holds the populations the graph starts from
     const float* gS = nullptr;      // source pointer the graph was captured with
-    const float* gdB = nullptr;     // space-dependent field pointer the graph was captured with
+    const float* gdB = nullptr;     // space-dependent field pointers the graph was captured with
+    const float* gCw = nullptr;
     int gkey[4] = {0, 0, 0, 0};     // tuning variables at capture (FP32 tile, BF16 tile, collide rows, stores)
 };
 

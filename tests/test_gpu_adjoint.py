@@ -2,8 +2,11 @@
 adjoint and against FP64 central differences.
 
 Tolerance: the reverse sweep runs in FP32 (fields) with FP64 scalar
-reductions; errors of the scalar gradients are measured relative to the
-largest gradient of the same group, and field gradients by relative L2.
+reductions.  Against the oracle adjoint on small grids, errors of the scalar
+gradients are measured relative to the largest scalar gradient (some
+components are near zero there), field gradients by relative L2; against
+central differences on the 512^2 workload every gradient is held to 1e-4 of
+its own value.
 """
 import json
 import os
@@ -209,7 +212,7 @@ GOLD = os.path.join(GOLDEN, "adjoint_c5_512sq_500steps.json")
 def test_adjoint_workload_against_fp64_central_differences():
     """512 x 512, 500 steps, checkpoint every 50: misfit-loss gradients with
     respect to D, u, p, C0 and S against FP64 central differences of the
-    oracle (bound 1e-4 relative)."""
+    oracle, each within 1e-4 of its own value."""
     gold = json.load(open(GOLD))
     hid = synth.config("c5_512sq_hidden")
     ev = synth.config("c5_512sq_eval")
@@ -236,7 +239,8 @@ def test_adjoint_workload_against_fp64_central_differences():
     for key, fd in gold["fd"].items():
         print(f"[gpu-adjoint] {key}: gpu {got[key]:.8e}  fd {fd:.8e}  oracle-adjoint {gold['adjoint'][key]:.8e}",
               flush=True)
-    for group in (("D00", "D11", "D01"), ("u0", "u1"), ("p0", "p1"), ("C0_dir0", "C0_dir1"), ("S_dir0", "S_dir1")):
-        scale = max(abs(gold["fd"][k]) for k in group)
-        for k in group:
-            assert abs(got[k] - gold["fd"][k]) <= 1e-4 * scale, (k, got[k], gold["fd"][k])
+    # every gradient to 1e-4 of its own value (none of them is near zero:
+    # the smallest, C0_dir1, is about -4.4 against a largest of 8.9e3)
+    for k, fd in gold["fd"].items():
+        assert abs(fd) > 1.0, (k, fd)
+        assert abs(got[k] - fd) <= 1e-4 * abs(fd), (k, got[k], fd)
