@@ -1,16 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the fractional LB time step on one MI355X.
 
-Workload: 2D, 1024 x 1024 nodes (walls included), D2Q5, MRT, FP32, 2000 steps;
-alpha = (1.3, 1.7), p = (0.3, 0.8), anisotropic D (eigenvalues 0.05 and 0.2
-rotated by 30 degrees), u = (0.05, 0.02); seeded sum of 8 Gaussian pulses,
-homogeneous Dirichlet walls.  One "step" is one full time step: the
-fractional-term GEMM along both axes and the fused collide-stream-boundary-
-moment kernel.  Inputs are resident in HBM before the timed region.
+Headline workload: 2D, 4096 x 4096 nodes (walls included), D2Q5, MRT, 1000
+steps; alpha = (1.2, 1.9), one-sided p = (1, 0), D = 0.1 Id, u = (0.02, 0.02);
+seeded sum of 8 Gaussian pulses, homogeneous Dirichlet walls; the
+fractional-term GEMM in FP32 (headline value) and in 3-term split BF16 on the
+matrix cores.  One "step" is one full time step: the fractional-term GEMM
+along both axes and the fused collide-stream-boundary-moment kernel.  Inputs
+are resident in HBM before the timed region.  Secondary blocks: the 1024^2
+(two-sided operators, rotated anisotropic D) and 256^3 (D3Q7, point source)
+workloads, and adjoint / forward on the 512^2 adjoint workload.
 
-Prints ONE JSON line.  Metric: MLUPS = nodes * steps / seconds / 1e6, with
-the relative L2 error of the final concentration against the FP64 oracle,
-for the FP32 GEMM (headline value) and the 3-term split-BF16 GEMM.
+Timing: the library replays a captured graph of 10 steps for runs of 10 or
+more steps; the graph is captured by an untimed 10-step run before the
+warm-up (then the state is reset), so no capture falls in a timed region.
+Each figure is the median of 5 timed runs of --steps steps (HIP events on
+the stream the kernels run on).  Accuracy: the relative L2 error of C after
+the workload's full step count against the stored FP64 oracle result, and
+of the fractional term of each axis (one alpha each) of the initial C.
+
+Prints ONE JSON line.  MLUPS = nodes * steps / seconds / 1e6.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -28,7 +37,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (incl. fractional-flux GEMM) FP32 vs split-BF16 at stated L2 error; adjoint/fwd"
-WORKLOAD = "c2_1024sq"
+WORKLOAD = "c4_4096sq"          # headline
+SECONDARY = ("c2_1024sq", "c3_256cube")
+GRAPH_STEPS = 10                # steps per captured step graph in the library
+REPEATS = 5
 PEAK = {"hbm_GBps": 8000.0, "fp32_mfma_TFLOPs": 157.3, "bf16_mfma_TFLOPs": 2500.0}
 
 
@@ -65,15 +77,26 @@ def collide_bytes_per_step(cfg: dict) -> float:
     return (2 * Q + d + 1) * 4.0 * float(np.prod(cfg["n"][:d]))
 
 
-def rel_l2_vs_reference(C: np.ndarray, name: str, steps: int):
-    path = os.path.join(ROOT, "tests", "golden", f"ref_{name}_{steps}steps_every4.npz")
-    if not os.path.exists(path):
-        return None
-    ref = np.load(path)
-    sl = (slice(None, None, int(ref["stride"])),) * C.ndim
-    got = C[sl].astype(np.float64)
-    r = ref["C"]
-    return float(np.linalg.norm((got - r).ravel()) / np.linalg.norm(r.ravel()))
+def reference_file(name: str, steps: int):
+    """Stored FP64 oracle result of a workload (tests/golden/make_reference.py), or None."""
+    import glob
+
+    hits = sorted(glob.glob(os.path.join(ROOT, "tests", "golden", f"ref_{name}_{steps}steps_every*.npz")))
+    return np.load(hits[0]) if hits else None
+
+
+def rel_l2(got: np.ndarray, ref: np.ndarray) -> float:
+    got = np.asarray(got, np.float64)
+    return float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def phi_reference(name: str):
+    """Stored FP64 oracle fractional terms of a workload's initial C
+    (tests/golden/make_phi_reference.py), or None."""
+    import glob
+
+    hits = sorted(glob.glob(os.path.join(ROOT, "tests", "golden", f"phi_{name}_C0_every*.npz")))
+    return np.load(hits[0]) if hits else None
 
 
 def time_steps(torch, solver, steps: int) -> float:
@@ -106,7 +129,7 @@ def time_gemm(torch, solver, reps: int) -> float:
     return start.elapsed_time(end) / 1e3 / reps
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_fp32__2d_1024sq_pmc.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_fp32__2d_4096sq_pmc.txt")
 GEMM_SOURCES = [os.path.join(ROOT, "paper_1706_09161_amd", "csrc", f) for f in ("fractional_gemm.hip", "lbm_internal.h")]
 
 
@@ -167,7 +190,8 @@ def profile_run(torch, LbmFade, synth, workload: str = WORKLOAD, reps: int = 20)
             s.set_C(C0)
             if S is not None:
                 s.set_source(S.astype(np.float32))
-            out = torch.empty((cfg["dim"],) + tuple(C0.shape), device="cuda")
+            # zero-filled, so the first GEMM launch does not pay the first touch of fresh memory
+            out = torch.zeros((cfg["dim"],) + tuple(C0.shape), device="cuda")
             for _ in range(reps):
                 s.apply_phi(None, out=out)
             s.step(reps)
@@ -194,62 +218,142 @@ def profile_adjoint(torch, LbmFade, synth):
     log("adjoint profile run done")
 
 
-def adjoint_ratio(torch, LbmFade, synth):
+def adjoint_ratio(torch, LbmFade, synth, repeats: int = 3):
     """Wall time of lbm_fade_adjoint(500 steps, checkpoint every 50) over that of
-    500 forward steps on the 512^2 adjoint workload (misfit gradient point)."""
+    500 forward steps on the 512^2 adjoint workload (misfit gradient point);
+    median of `repeats` timings of each, after an untimed run of each (it
+    allocates the checkpoints and captures the step graph)."""
     cfg = synth.config("c5_512sq_eval")
     steps, K = cfg["steps"], cfg["ckpt_every"]
     C0 = torch.from_numpy(synth.initial_C(cfg).astype(np.float32)).cuda()
     gC = torch.from_numpy(np.random.default_rng(5).standard_normal(synth.shape(cfg)).astype(np.float32)).cuda()
+    fwd, adj = [], []
     with LbmFade.from_config(cfg, precision="fp32") as s:
         s.set_C(C0)
-        s.adjoint(steps, K, gC)  # warm-up (allocates checkpoints)
-        s.set_C(C0)
-        s.step(steps)  # warm-up (captures the step graph)
-        s.set_C(C0)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        s.step(steps)
-        torch.cuda.synchronize()
-        fwd = time.perf_counter() - t
-        s.set_C(C0)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
         s.adjoint(steps, K, gC)
-        adj = time.perf_counter() - t
-    return {"value": round(adj / fwd, 3), "adjoint_ms": adj * 1e3, "forward_ms": fwd * 1e3,
+        s.set_C(C0)
+        s.step(steps)
+        for _ in range(repeats):
+            s.set_C(C0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            s.step(steps)
+            torch.cuda.synchronize()
+            fwd.append(time.perf_counter() - t)
+            s.set_C(C0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            s.adjoint(steps, K, gC)  # synchronises (scalar gradients to the host)
+            adj.append(time.perf_counter() - t)
+    f, a = float(np.median(fwd)), float(np.median(adj))
+    return {"value": round(a / f, 3), "adjoint_ms": a * 1e3, "forward_ms": f * 1e3, "repeats": repeats,
             "workload": "2D 512x512 D2Q5 MRT, 500 steps, checkpoint every 50, FP32"}
 
 
-def cpu_baseline(cfg: dict, budget_s: float = 15.0):
-    """The FP64 oracle as it stands, on the host's cores, for a bounded number of
-    steps of the same workload (starting from its initial state)."""
+def cpu_baseline(cfg: dict, min_s: float = 10.0):
+    """The FP64 oracle as it stands, on the host's cores, on a bounded sample of
+    the same workload: whole steps from its initial state, at least one and
+    at least `min_s` seconds (the set-up of the initial populations is not
+    timed)."""
     import oracle
     import synth
 
     C0 = synth.initial_C(cfg).astype(np.float32).astype(np.float64)
     f = oracle.init(cfg, C0)
-    t = time.perf_counter()
-    f = oracle.step(cfg, f, 1)
-    one = time.perf_counter() - t
-    steps = int(max(1, min(200, budget_s / max(one, 1e-3))))
-    t = time.perf_counter()
-    oracle.step(cfg, f, steps)
-    dt = time.perf_counter() - t
+    S = synth.source(cfg)
+    steps, dt = 0, 0.0
+    while steps == 0 or dt < min_s:
+        k = 1 if steps == 0 else max(1, int(np.ceil((min_s - dt) / (dt / steps))))
+        t = time.perf_counter()
+        f = oracle.step(cfg, f, k, S)
+        dt += time.perf_counter() - t
+        steps += k
     nodes = float(np.prod(cfg["n"][: cfg["dim"]]))
+    shape = "x".join(str(v) for v in cfg["n"][: cfg["dim"]])
     return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{steps} steps of the same {cfg['n'][0]}x{cfg['n'][1]} workload (FP64, OpenMP over lines), "
-                      f"{dt:.1f} s"}
+            "sample": f"{steps} step(s) of the same {shape} workload from its initial state (FP64, OpenMP over "
+                      f"lines), {dt:.1f} s"}
+
+
+def describe(cfg: dict) -> str:
+    d = cfg["dim"]
+    shape = "x".join(str(v) for v in cfg["n"][:d])
+    lat = "D2Q5" if d == 2 else "D3Q7"
+    D = np.asarray(cfg["D"], dtype=np.float64)
+    Ds = (f"D={D[0, 0]:g} Id" if np.allclose(D, D[0, 0] * np.eye(d)) else
+          "D=" + str(np.round(D, 6).tolist()))
+    src = ", point source" if cfg.get("source") else ""
+    fmt = lambda v: "(" + ",".join(f"{x:g}" for x in v) + ")"  # noqa: E731
+    return (f"{d}D {shape} {lat} {cfg.get('collision', 'MRT')}, alpha={fmt(cfg['alpha'])}, p={fmt(cfg['p'])}, "
+            f"{Ds}, u={fmt(cfg['u'])}, {cfg['steps']} steps{src}, Dirichlet 0")
+
+
+def measure(torch, LbmFade, synth, name: str, steps: int, warmup: int, repeats: int, accuracy: bool):
+    """FP32 and split-BF16 figures of one workload: median step time of
+    `repeats` timed runs, median GEMM launch time, accuracy vs the oracle."""
+    cfg = synth.config(name)
+    d = cfg["dim"]
+    nodes = int(np.prod(cfg["n"][:d]))
+    C0 = torch.from_numpy(synth.initial_C(cfg).astype(np.float32)).cuda()
+    S = synth.source(cfg)
+    S = None if S is None else torch.from_numpy(S.astype(np.float32)).cuda()
+    ref = reference_file(name, cfg["steps"]) if accuracy else None
+    phi_ref = phi_reference(name) if accuracy else None
+    out = {}
+    for precision in ("fp32", "bf16x3"):
+        log(f"{name} {precision}: create")
+        with LbmFade.from_config(cfg, precision=precision) as s:
+            s.set_C(C0)
+            s.set_source(S)
+            s.step(GRAPH_STEPS)  # captures the step graph; not timed, not a warm-up step
+            s.set_C(C0)
+            s.step(warmup)
+            secs = sorted(time_steps(torch, s, steps) for _ in range(repeats))
+            gemm = sorted(time_gemm(torch, s, reps=max(10, min(200, steps))) for _ in range(repeats))
+            r = {"secs": float(np.median(secs)), "secs_all": secs, "gemm_s": float(np.median(gemm))}
+            log(f"{name} {precision}: {steps} steps in {r['secs'] * 1e3:.3f} ms (median of {repeats}); "
+                f"GEMM {r['gemm_s'] * 1e6:.1f} us")
+            if accuracy:
+                if phi_ref is not None:
+                    phi = s.apply_phi(C0).cpu().numpy()
+                    st = int(phi_ref["stride"])
+                    sl = (slice(None),) + (slice(None, None, st),) * d
+                    r["phi_err_per_axis"] = [rel_l2(phi[sl][mu], phi_ref["Phi"][mu]) for mu in range(d)]
+                s.set_C(C0)
+                s.step(cfg["steps"])
+                C = s.get_C(device=False)
+                if ref is not None:
+                    st = int(ref["stride"])
+                    r["err"] = rel_l2(C[(slice(None, None, st),) * d], ref["C"])
+                log(f"{name} {precision}: rel L2 vs FP64 oracle after {cfg['steps']} steps = {r.get('err')}, "
+                    f"Phi per axis {r.get('phi_err_per_axis')}")
+        out[precision] = r
+    flops = gemm_flops_per_step(cfg)
+    blk = {"workload": describe(cfg), "nodes": nodes}
+    for precision, key in (("fp32", "fp32"), ("bf16x3", "split_bf16")):
+        r = out[precision]
+        terms = 1 if precision == "fp32" else 3
+        peak = PEAK["fp32_mfma_TFLOPs"] if precision == "fp32" else PEAK["bf16_mfma_TFLOPs"]
+        gemm_tf = terms * flops / r["gemm_s"] / 1e12
+        collide_s = max(r["secs"] / steps - r["gemm_s"], 1e-12)
+        blk[key] = {"MLUPS": round(nodes * steps / r["secs"] / 1e6, 2), "us_per_step": r["secs"] / steps * 1e6,
+                    "rel_l2_vs_fp64_oracle": r.get("err"), "phi_rel_l2_per_axis": r.get("phi_err_per_axis"),
+                    "gemm_us": r["gemm_s"] * 1e6, "gemm_TFLOPs": round(gemm_tf, 2),
+                    "gemm_frac_of_peak": round(gemm_tf / peak, 4),
+                    "collide_us_step_minus_gemm": collide_s * 1e6,
+                    "collide_GBps_step_minus_gemm": collide_bytes_per_step(cfg) / collide_s / 1e9}
+    return cfg, out, blk
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000, help="timed steps (default: the workload's 2000)")
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100, help="timed steps per run (median of 5 runs)")
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the full-length accuracy runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 1024^2 and 256^3 blocks")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the launch sequence profiled by rocprofv3 (copy calibration, GEMM, steps); no JSON")
     ap.add_argument("--profile-workload", default=WORKLOAD,
@@ -276,41 +380,17 @@ def main():
     if args.profile_adjoint:
         profile_adjoint(torch, LbmFade, synth)
         return
-    cfg = synth.config(WORKLOAD)
+
+    cfg, res, head = measure(torch, LbmFade, synth, WORKLOAD, args.steps, args.warmup, REPEATS,
+                             not args.no_accuracy)
     d = cfg["dim"]
     nodes = int(np.prod(cfg["n"][:d]))
-    C0 = torch.from_numpy(synth.initial_C(cfg).astype(np.float32)).cuda()
-
-    results = {}
-    for precision in ("fp32", "bf16x3"):
-        log(f"{precision}: create")
-        try:
-            s = LbmFade.from_config(cfg, precision=precision)
-        except Exception as e:  # the BF16 kernel may be absent from an older build
-            log(f"{precision}: unavailable ({e})")
-            continue
-        with s:
-            s.set_C(C0)
-            s.step(args.warmup)
-            secs = time_steps(torch, s, args.steps)
-            log(f"{precision}: {args.steps} steps in {secs * 1e3:.2f} ms")
-            gemm_s = time_gemm(torch, s, reps=max(20, min(500, args.steps)))
-            err = None
-            if not args.no_accuracy:
-                s.set_C(C0)
-                s.step(cfg["steps"])
-                err = rel_l2_vs_reference(s.get_C(device=False), WORKLOAD, cfg["steps"])
-                log(f"{precision}: rel L2 vs FP64 oracle after {cfg['steps']} steps = {err}")
-        results[precision] = {"secs": secs, "gemm_s": gemm_s, "err": err}
-
-    r = results["fp32"]
-    mlups = nodes * args.steps / r["secs"] / 1e6
+    r = res["fp32"]
     flops = gemm_flops_per_step(cfg)
     achieved = flops / r["gemm_s"] / 1e12
-    collide_s = max(r["secs"] / args.steps - r["gemm_s"], 1e-12)
     line = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": head["fp32"]["MLUPS"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -321,29 +401,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D 1024x1024 D2Q5 MRT, alpha=(1.3,1.7), p=(0.3,0.8), rotated anisotropic D, "
-                               "u=(0.05,0.02), 8 seeded Gaussian pulses, Dirichlet 0, FP32 GEMM",
-                   "nodes": nodes, "workload_steps": cfg["steps"]},
-        "rel_l2_vs_fp64_oracle": r["err"],
+        "config": {"workload": head["workload"] + "; fractional-flux GEMM FP32 (value) vs 3-term split BF16",
+                   "nodes": nodes, "workload_steps": cfg["steps"], "timed_runs": REPEATS,
+                   "statistic": "median"},
+        "rel_l2_vs_fp64_oracle": head["fp32"]["rel_l2_vs_fp64_oracle"],
+        "phi_rel_l2_per_axis": head["fp32"]["phi_rel_l2_per_axis"],
+        "alpha_per_axis": cfg["alpha"],
+        "split_bf16": head["split_bf16"],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp32_mfma_TFLOPs"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32_mfma_TFLOPs"], 4),
                      "traffic": measured_traffic(),
                      "kernel": "fractional-term GEMM, FP32 (one launch: x and y axes of a step)",
                      "flops_per_launch": flops, "avg_us_per_launch": r["gemm_s"] * 1e6,
                      "algorithmic_bytes_per_launch": gemm_bytes_per_step(cfg)},
-        "collide_stream": {"bound": "hbm", "est_us_per_step": collide_s * 1e6,
-                           "algorithmic_bytes_per_step": collide_bytes_per_step(cfg),
-                           "achieved_GBps": collide_bytes_per_step(cfg) / collide_s / 1e9,
-                           "peak_GBps": PEAK["hbm_GBps"]},
+        "fp32_detail": head["fp32"],
     }
-    if "bf16x3" in results:
-        b = results["bf16x3"]
-        bach = 3 * flops / b["gemm_s"] / 1e12
-        line["split_bf16"] = {"value": round(nodes * args.steps / b["secs"] / 1e6, 2), "unit": "MLUPS",
-                              "ms_per_step": b["secs"] / args.steps * 1e3, "rel_l2_vs_fp64_oracle": b["err"],
-                              "gemm_us_per_step": b["gemm_s"] * 1e6,
-                              "gemm_mfma_TFLOPs_3terms": round(bach, 3),
-                              "gemm_frac_of_bf16_peak": round(bach / PEAK["bf16_mfma_TFLOPs"], 4)}
+    if not args.no_secondary:
+        line["secondary"] = {}
+        for name in SECONDARY:
+            try:
+                _, _, blk = measure(torch, LbmFade, synth, name, args.steps, args.warmup, REPEATS,
+                                    not args.no_accuracy)
+                line["secondary"][name] = blk
+            except Exception as e:  # reported, never fatal for the headline line
+                line["secondary"][name] = {"error": str(e)}
     if not args.no_adjoint:
         try:
             log("adjoint / forward")

@@ -70,23 +70,5 @@ def build(extra_flags: list[str] | None = None, verbose: bool = False) -> str:
     return LIB
 
 
-# The streaming-bandwidth probe that sits beside bench.py (a measurement
-# helper, not part of the library).
-HBM_PROBE_SRC = os.path.join(os.path.dirname(HERE), "bench_hbm_ceiling.hip")
-HBM_PROBE = os.path.join(os.path.dirname(HERE), "bench_hbm_ceiling")
-
-
-def build_hbm_probe(verbose: bool = False) -> str:
-    """Compile bench_hbm_ceiling.hip into an executable next to bench.py."""
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", HBM_PROBE_SRC, "-o", HBM_PROBE]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {HBM_PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
-    if verbose:
-        print(f"built {HBM_PROBE}")
-    return HBM_PROBE
-
-
 if __name__ == "__main__":
     build(sys.argv[1:], verbose=True)
