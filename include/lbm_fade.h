@@ -177,6 +177,28 @@ LBM_API int lbm_fade_set_f(lbm_fade_t h, const float* src, int32_t on_device, vo
  * Does not touch the solver state. */
 LBM_API int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t on_device, void* stream);
 
+/* The operator of lbm_fade_apply_phi without a handle and without any device
+ * allocation, for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, hosts that forbid hipMalloc).
+ * grid and params are as for lbm_fade_create (same checks, same FP64 weight
+ * generation, same kernels: the result equals lbm_fade_apply_phi on a handle
+ * created with them, bit for bit).  C (nodes floats) and Phi (dim * nodes
+ * floats, Phi[mu*nodes + node]) are device pointers on the current device,
+ * ordered on `stream`; they are only borrowed.  The operator data and, with
+ * LBM_BF16X3, the packed split of C are placed in a fixed device array of
+ * LBM_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
+ * runs on until the process ends: the call needs about 40 n bytes per axis of
+ * n nodes (plus 4 bytes per node with LBM_BF16X3) and returns LBM_EINVAL,
+ * naming the size, for a grid beyond that.  Every call on a device uses that
+ * device's one array, so calls that overlap on one device (other host threads,
+ * or other streams before this call's kernels have finished) race; calls
+ * ordered on one stream are safe.  Synchronises `stream` once (after copying
+ * the host-built operator data into the array); the fractional-term kernels
+ * are then queued on `stream`. */
+#define LBM_NOALLOC_SCRATCH_BYTES (16u << 20)
+LBM_API int lbm_fade_apply_phi_noalloc(const lbm_grid* grid, const lbm_params* params, const float* C, float* Phi,
+                                       void* stream);
+
 /* Gradients reported by lbm_fade_adjoint (FP64). */
 typedef struct {
     double dD[9]; /* d x d, symmetrised: dL = sum_ab dD_ab deltaD_ab for every symmetric

@@ -12,6 +12,7 @@ LBM_D2Q5, LBM_D3Q7 = 5, 7
 LBM_BGK, LBM_MRT = 0, 1
 LBM_FP32, LBM_BF16X3, LBM_FP32_SIMT = 0, 1, 2
 LBM_FLUX_RL, LBM_FLUX_CAPUTO = 0, 1
+LBM_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 ERROR_NAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM", LBM_EDEVICE: "LBM_EDEVICE",
                LBM_ENONFINITE: "LBM_ENONFINITE", LBM_ESTATE: "LBM_ESTATE"}
@@ -19,7 +20,8 @@ ERROR_NAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM", LBM_EDEVICE: 
 # Every symbol include/lbm_fade.h declares.
 EXPORTED = ["lbm_fade_create", "lbm_fade_destroy", "lbm_fade_set_C", "lbm_fade_set_source", "lbm_fade_set_diffusion",
             "lbm_fade_set_wall", "lbm_fade_step",
-            "lbm_fade_get_C", "lbm_fade_get_f", "lbm_fade_set_f", "lbm_fade_apply_phi", "lbm_fade_adjoint",
+            "lbm_fade_get_C", "lbm_fade_get_f", "lbm_fade_set_f", "lbm_fade_apply_phi", "lbm_fade_apply_phi_noalloc",
+            "lbm_fade_adjoint",
             "lbm_fade_last_error", "lbm_fade_version", "lbm_rw_init_gaussian", "lbm_rw_walk", "lbm_rw_histogram"]
 
 
@@ -97,6 +99,8 @@ def lib() -> ctypes.CDLL:
         "lbm_fade_get_f": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),
         "lbm_fade_set_f": (ctypes.c_int, [H, fp, ctypes.c_int32, vp]),
         "lbm_fade_apply_phi": (ctypes.c_int, [H, fp, fp, ctypes.c_int32, vp]),
+        "lbm_fade_apply_phi_noalloc": (ctypes.c_int, [ctypes.POINTER(lbm_grid), ctypes.POINTER(lbm_params), fp, fp,
+                                                      vp]),
         "lbm_fade_adjoint": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int32, fp, ctypes.c_int32,
                                             ctypes.POINTER(lbm_grads), fp, fp, vp]),
         "lbm_rw_init_gaussian": (ctypes.c_int, [ctypes.POINTER(lbm_rw_params), ctypes.POINTER(ctypes.c_double),

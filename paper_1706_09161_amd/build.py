@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmfade.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["lbm_fade.hip", "fractional_gemm.hip", "fractional_gemm_bf16.hip", "collide_stream.hip", "adjoint.hip",
-           "random_walk.hip"]
+           "random_walk.hip", "apply_phi_noalloc.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for device code; the host pass warns

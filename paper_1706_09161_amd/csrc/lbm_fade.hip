@@ -525,6 +525,104 @@ int diffusion_blocks(lbm_fade* h, const float* D, std::vector<float>& out)
 }  // namespace
 
 namespace lbm {
+
+int validate_config(const lbm_grid* grid, int32_t lattice, const lbm_params* params)
+{
+    return validate(grid, lattice, params);
+}
+
+// Every piece of the operator data sits at a 256-byte aligned offset.
+static size_t r256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t operator_image_bytes(const lbm_grid& grid)
+{
+    size_t bytes = 0;
+    for (int mu = 0; mu < grid.dim; ++mu) {
+        const size_t n = (size_t)grid.n[mu];
+        bytes += r256(sizeof(float) * (2 * n - 1)) + 2 * r256(sizeof(float) * n) +
+                 2 * r256(sizeof(uint16_t) * (2 * n - 1)) + 2 * r256(sizeof(uint32_t) * pw_len_of((int)n));
+    }
+    return bytes;
+}
+
+void build_operator_image(const lbm_grid& grid, const lbm_params& P, unsigned char* host, const unsigned char* base,
+                          AxisOp* ops)
+{
+    size_t off = 0;
+    auto carve = [&](size_t nbytes) {
+        const size_t o = off;
+        off += r256(nbytes);
+        return o;
+    };
+    for (int mu = 0; mu < grid.dim; ++mu) {
+        const int n = grid.n[mu];
+        const AxisWeights W = make_axis_weights(n, 2.0 - P.alpha[mu], P.p[mu], P.g[mu], grid.dx, P.flux_form);
+        AxisOp& op = ops[mu];
+        op.n = n;
+        op.lower_only = P.p[mu] == 1.0;
+        op.upper_only = P.p[mu] == 0.0;
+        const size_t og = carve(sizeof(float) * (2 * n - 1));
+        const size_t o0 = carve(sizeof(float) * n);
+        const size_t oN = carve(sizeof(float) * n);
+        const size_t oh = carve(sizeof(uint16_t) * (2 * n - 1));
+        const size_t ol = carve(sizeof(uint16_t) * (2 * n - 1));
+        const int64_t pwn = pw_len_of(n);
+        const size_t oph = carve(sizeof(uint32_t) * pwn);
+        const size_t opl = carve(sizeof(uint32_t) * pwn);
+        float* g = reinterpret_cast<float*>(host + og);
+        float* c0 = reinterpret_cast<float*>(host + o0);
+        float* cN = reinterpret_cast<float*>(host + oN);
+        uint16_t* gh = reinterpret_cast<uint16_t*>(host + oh);
+        uint16_t* glo = reinterpret_cast<uint16_t*>(host + ol);
+        for (int t = 0; t < 2 * n - 1; ++t) {
+            const double v = W.T[t];
+            g[t] = (float)v;
+            gh[t] = bf16_from_double(v);
+            glo[t] = bf16_from_double(v - (double)bf16_to_float(gh[t]));
+        }
+        for (int j = 0; j < n; ++j) {
+            c0[j] = (float)W.corr0[j];
+            cN[j] = (float)W.corrN[j];
+        }
+        // pair words of the BF16 split, d decreasing (operand order of the BF16 GEMM)
+        uint32_t* pwh = reinterpret_cast<uint32_t*>(host + oph);
+        uint32_t* pwl = reinterpret_cast<uint32_t*>(host + opl);
+        const int top = pw_top_of(n);
+        auto bits = [&](const uint16_t* b, int64_t dd) -> uint32_t {
+            return (dd >= -(n - 1) && dd <= n - 1) ? (uint32_t)b[dd + n - 1] : 0u;
+        };
+        for (int64_t x = 0; x < pwn; ++x) {
+            const int64_t dd = top - x;
+            pwh[x] = bits(gh, dd) | (bits(gh, dd - 1) << 16);
+            pwl[x] = bits(glo, dd) | (bits(glo, dd - 1) << 16);
+        }
+        op.gen = reinterpret_cast<const float*>(base + og);
+        op.corr0 = reinterpret_cast<const float*>(base + o0);
+        op.corrN = reinterpret_cast<const float*>(base + oN);
+        op.gen_hi = reinterpret_cast<const uint16_t*>(base + oh);
+        op.gen_lo = reinterpret_cast<const uint16_t*>(base + ol);
+        op.pw_hi = reinterpret_cast<const uint32_t*>(base + oph);
+        op.pw_lo = reinterpret_cast<const uint32_t*>(base + opl);
+        op.pw_top = top;
+    }
+}
+
+void make_layouts(const lbm_grid& grid, AxisLayout* lays)
+{
+    const int64_t nx = grid.n[0], ny = grid.n[1], nz = grid.dim == 3 ? grid.n[2] : 1;
+    const int64_t nodes = nx * ny * nz;
+    lays[0] = {1, nodes / nx, 1, 0, 1};
+    if (grid.dim == 2) {
+        lays[1] = {0, nx, nx, 0, 1};
+    } else {
+        lays[1] = {0, nx, nx, nx * ny, (int)nz};
+        lays[2] = {0, nx * ny, nx * ny, 0, 1};
+    }
+}
+
+}  // namespace lbm
+
+namespace lbm {
 // used by the adjoint driver
 int fade_run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s) { return run_phi(h, C, Phi, s); }
 int fade_forward_step(lbm_fade* h, hipStream_t s) { return forward_step(h, s); }
@@ -588,17 +686,7 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
     cc.c_wall = (float)params->c_wall;
 
     // operator data
-    // every piece is placed at a 256-byte aligned offset
-    auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    size_t bytes = 0;
-    std::vector<AxisWeights> W(d);
-    for (int mu = 0; mu < d; ++mu) {
-        const size_t n = (size_t)grid->n[mu];
-        W[mu] = make_axis_weights((int)n, 2.0 - params->alpha[mu], params->p[mu], params->g[mu], grid->dx,
-                                  params->flux_form);
-        bytes += r256(sizeof(float) * (2 * n - 1)) + 2 * r256(sizeof(float) * n) +
-                 2 * r256(sizeof(uint16_t) * (2 * n - 1)) + 2 * r256(sizeof(uint32_t) * lbm::pw_len_of((int)n));
-    }
+    const size_t bytes = lbm::operator_image_bytes(*grid);
     auto cleanup = [&]() { lbm_fade_destroy(h); };
     hipError_t e = hipMalloc(&h->opmem, bytes);
     if (e != hipSuccess) {
@@ -606,85 +694,13 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
         return fail(LBM_ENOMEM, "hipMalloc of operator data failed");
     }
     std::vector<unsigned char> host(bytes, 0);
-    size_t off = 0;
-    auto carve = [&](size_t nbytes) {
-        size_t o = off;
-        off += r256(nbytes);
-        return o;
-    };
-    for (int mu = 0; mu < d; ++mu) {
-        const int n = grid->n[mu];
-        lbm::AxisOp& op = h->ops[mu];
-        op.n = n;
-        op.lower_only = params->p[mu] == 1.0;
-        op.upper_only = params->p[mu] == 0.0;
-        const size_t og = carve(sizeof(float) * (2 * n - 1));
-        const size_t o0 = carve(sizeof(float) * n);
-        const size_t oN = carve(sizeof(float) * n);
-        const size_t oh = carve(sizeof(uint16_t) * (2 * n - 1));
-        const size_t ol = carve(sizeof(uint16_t) * (2 * n - 1));
-        const int64_t pwn = lbm::pw_len_of(n);
-        const size_t oph = carve(sizeof(uint32_t) * pwn);
-        const size_t opl = carve(sizeof(uint32_t) * pwn);
-        if (off > bytes) {
-            cleanup();
-            return fail(LBM_EINVAL, "internal: operator buffer overflow");
-        }
-        float* g = reinterpret_cast<float*>(host.data() + og);
-        float* c0 = reinterpret_cast<float*>(host.data() + o0);
-        float* cN = reinterpret_cast<float*>(host.data() + oN);
-        uint16_t* gh = reinterpret_cast<uint16_t*>(host.data() + oh);
-        uint16_t* glo = reinterpret_cast<uint16_t*>(host.data() + ol);
-        for (int t = 0; t < 2 * n - 1; ++t) {
-            const double v = W[mu].T[t];
-            g[t] = (float)v;
-            gh[t] = bf16_from_double(v);
-            glo[t] = bf16_from_double(v - (double)bf16_to_float(gh[t]));
-        }
-        for (int j = 0; j < n; ++j) {
-            c0[j] = (float)W[mu].corr0[j];
-            cN[j] = (float)W[mu].corrN[j];
-        }
-        // pair words of the BF16 split, d decreasing (operand order of the BF16 GEMM)
-        uint32_t* pwh = reinterpret_cast<uint32_t*>(host.data() + oph);
-        uint32_t* pwl = reinterpret_cast<uint32_t*>(host.data() + opl);
-        const int top = lbm::pw_top_of(n);
-        auto bits = [&](const uint16_t* b, int64_t dd) -> uint32_t {
-            return (dd >= -(n - 1) && dd <= n - 1) ? (uint32_t)b[dd + n - 1] : 0u;
-        };
-        for (int64_t x = 0; x < pwn; ++x) {
-            const int64_t dd = top - x;
-            pwh[x] = bits(gh, dd) | (bits(gh, dd - 1) << 16);
-            pwl[x] = bits(glo, dd) | (bits(glo, dd - 1) << 16);
-        }
-        unsigned char* base = reinterpret_cast<unsigned char*>(h->opmem);
-        op.gen = reinterpret_cast<const float*>(base + og);
-        op.corr0 = reinterpret_cast<const float*>(base + o0);
-        op.corrN = reinterpret_cast<const float*>(base + oN);
-        op.gen_hi = reinterpret_cast<const uint16_t*>(base + oh);
-        op.gen_lo = reinterpret_cast<const uint16_t*>(base + ol);
-        op.pw_hi = reinterpret_cast<const uint32_t*>(base + oph);
-        op.pw_lo = reinterpret_cast<const uint32_t*>(base + opl);
-        op.pw_top = top;
-    }
-    if (off > bytes) {
-        cleanup();
-        return fail(LBM_EINVAL, "internal: operator buffer overflow");
-    }
-    e = hipMemcpy(h->opmem, host.data(), off, hipMemcpyHostToDevice);
+    lbm::build_operator_image(*grid, *params, host.data(), reinterpret_cast<const unsigned char*>(h->opmem), h->ops);
+    e = hipMemcpy(h->opmem, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         cleanup();
         return fail(LBM_EDEVICE, std::string("upload of operator data failed: ") + hipGetErrorString(e));
     }
-    // layouts
-    const int64_t nx = grid->n[0], ny = grid->n[1], nz = d == 3 ? grid->n[2] : 1;
-    h->lays[0] = {1, h->nodes / nx, 1, 0, 1};
-    if (d == 2) {
-        h->lays[1] = {0, nx, nx, 0, 1};
-    } else {
-        h->lays[1] = {0, nx, nx, nx * ny, (int)nz};
-        h->lays[2] = {0, nx * ny, nx * ny, 0, 1};
-    }
+    lbm::make_layouts(*grid, h->lays);
     // state
     const size_t fbytes = sizeof(float) * Q * h->nodes;
     if (hipMalloc(&h->f[0], fbytes) != hipSuccess || hipMalloc(&h->f[1], fbytes) != hipSuccess ||

@@ -68,6 +68,17 @@ int fade_run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s);
 // One forward time step of the handle's state (fractional term, then the
 // fused collide-stream kernel, which also refreshes C and its BF16 split).
 int fade_forward_step(lbm_fade* h, hipStream_t s);
+// Parameter checks of lbm_fade_create (error message set on failure).
+int validate_config(const lbm_grid* grid, int32_t lattice, const lbm_params* params);
+// Operator data of every axis (Toeplitz generator, boundary columns, BF16
+// splits and pair words) as one host image of operator_image_bytes(grid)
+// bytes, built in FP64; ops[mu] receives the device pointers the image has
+// once copied to `base`.
+size_t operator_image_bytes(const lbm_grid& grid);
+void build_operator_image(const lbm_grid& grid, const lbm_params& params, unsigned char* host,
+                          const unsigned char* base, AxisOp* ops);
+// Strided views of a node field for the operator along each axis.
+void make_layouts(const lbm_grid& grid, AxisLayout* lays);
 // Adjoint driver (adjoint.hip).
 int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_device, lbm_grads* out,
                 float* dC0, float* dS, hipStream_t s, std::string& msg);

@@ -44,6 +44,49 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(0)
 
 
+def make_structs(dim: int, n, *, alpha, p, D, g=None, u=None, dx: float = 1.0, dt: float = 1.0, tau_free=None,
+                 tau0: float = 1.0, c_wall: float = 0.0, collision: str = "MRT", precision: str = "fp32",
+                 nonfinite_check_every: int = 0, flux_form: str = "rl"):
+    """The ABI's lbm_grid and lbm_params for these arguments (see LbmFade)."""
+    d = int(dim)
+    n = [int(v) for v in n][:d]
+    grid = L.lbm_grid()
+    grid.dim = d
+    for mu in range(3):
+        grid.n[mu] = n[mu] if mu < d else 1
+    grid.dx, grid.dt = float(dx), float(dt)
+    P = L.lbm_params()
+    g = [1.0] * d if g is None else list(g)
+    u = [0.0] * d if u is None else list(u)
+    tf = [1.0] * 4 if tau_free is None else list(tau_free) + [1.0] * (4 - len(tau_free))
+    Dm = np.asarray(D, dtype=np.float64).reshape(d, d)
+    for mu in range(d):
+        P.alpha[mu] = float(alpha[mu])
+        P.p[mu] = float(p[mu])
+        P.g[mu] = float(g[mu])
+        P.u[mu] = float(u[mu])
+    for a in range(d):
+        for b in range(d):
+            P.D[a * d + b] = float(Dm[a, b])
+    for k in range(4):
+        P.tau_free[k] = float(tf[k])
+    P.tau0 = float(tau0)
+    P.c_wall = float(c_wall)
+    P.collision = _COLLISION[collision]
+    P.precision = _PRECISION[precision]
+    P.nonfinite_check_every = int(nonfinite_check_every)
+    P.flux_form = _FLUX_FORM[flux_form]
+    return grid, P
+
+
+def config_kwargs(cfg: dict) -> dict:
+    """Solver keyword arguments of a plain configuration dict (see ``synth``)."""
+    return dict(alpha=cfg["alpha"], p=cfg["p"], D=cfg["D"], g=cfg.get("g"), u=cfg.get("u"), dx=cfg.get("dx", 1.0),
+                dt=cfg.get("dt", 1.0), tau_free=cfg.get("tau_free"), tau0=cfg.get("tau0", 1.0),
+                c_wall=cfg.get("c_wall", 0.0), collision=cfg.get("collision", "MRT"),
+                flux_form=cfg.get("flux_form", "rl"))
+
+
 class LbmFade:
     """One solver (one grid, one parameter set) on the current HIP device."""
 
@@ -56,33 +99,9 @@ class LbmFade:
         self.Q = 2 * self.dim + 1
         self.nodes = int(np.prod(self.n))
         self.shape = tuple(reversed(self.n))  # slowest axis first
-        grid = L.lbm_grid()
-        grid.dim = self.dim
-        for mu in range(3):
-            grid.n[mu] = self.n[mu] if mu < self.dim else 1
-        grid.dx, grid.dt = float(dx), float(dt)
-        P = L.lbm_params()
-        d = self.dim
-        g = [1.0] * d if g is None else list(g)
-        u = [0.0] * d if u is None else list(u)
-        tf = [1.0] * 4 if tau_free is None else list(tau_free) + [1.0] * (4 - len(tau_free))
-        Dm = np.asarray(D, dtype=np.float64).reshape(d, d)
-        for mu in range(d):
-            P.alpha[mu] = float(alpha[mu])
-            P.p[mu] = float(p[mu])
-            P.g[mu] = float(g[mu])
-            P.u[mu] = float(u[mu])
-        for a in range(d):
-            for b in range(d):
-                P.D[a * d + b] = float(Dm[a, b])
-        for k in range(4):
-            P.tau_free[k] = float(tf[k])
-        P.tau0 = float(tau0)
-        P.c_wall = float(c_wall)
-        P.collision = _COLLISION[collision]
-        P.precision = _PRECISION[precision]
-        P.nonfinite_check_every = int(nonfinite_check_every)
-        P.flux_form = _FLUX_FORM[flux_form]
+        grid, P = make_structs(dim, n, alpha=alpha, p=p, D=D, g=g, u=u, dx=dx, dt=dt, tau_free=tau_free, tau0=tau0,
+                               c_wall=c_wall, collision=collision, precision=precision,
+                               nonfinite_check_every=nonfinite_check_every, flux_form=flux_form)
         h = ctypes.c_void_p()
         L.check(lib.lbm_fade_create(ctypes.byref(grid), self.Q, ctypes.byref(P), ctypes.byref(h)))
         self._h = h
@@ -92,10 +111,7 @@ class LbmFade:
     @classmethod
     def from_config(cls, cfg: dict, precision: str = "fp32", **kw) -> "LbmFade":
         d = cfg["dim"]
-        return cls(d, cfg["n"][:d], alpha=cfg["alpha"], p=cfg["p"], D=cfg["D"], g=cfg.get("g"), u=cfg.get("u"),
-                   dx=cfg.get("dx", 1.0), dt=cfg.get("dt", 1.0), tau_free=cfg.get("tau_free"),
-                   tau0=cfg.get("tau0", 1.0), c_wall=cfg.get("c_wall", 0.0), collision=cfg.get("collision", "MRT"),
-                   precision=precision, flux_form=cfg.get("flux_form", "rl"), **kw)
+        return cls(d, cfg["n"][:d], precision=precision, **config_kwargs(cfg), **kw)
 
     # -- lifetime -------------------------------------------------------------
     def close(self):
@@ -228,6 +244,31 @@ class LbmFade:
             "p": np.array(g.dp[:d]),
         }
         return grads, dC0, dS
+
+
+def apply_phi_noalloc(dim: int, n, C, out=None, stream=None, **params):
+    """lbm_fade_apply_phi_noalloc: the fractional operator of every axis for the
+    device field C without a handle (no device allocation in the library).
+    params are LbmFade's keyword arguments; C and out are CUDA tensors (out:
+    float32, contiguous, shape (dim, *C.shape); allocated here when None)."""
+    grid, P = make_structs(dim, n, **params)
+    if not _is_cuda_tensor(C):
+        raise ValueError("C must be a CUDA tensor")
+    torch = _torch()
+    c = C.detach()
+    if c.dtype != torch.float32 or not c.is_contiguous():
+        c = c.to(torch.float32).contiguous()
+    nodes = int(np.prod([int(v) for v in n][: int(dim)]))
+    if c.numel() != nodes:
+        raise ValueError(f"expected {nodes} values, got {c.numel()}")
+    if out is None:
+        out = torch.empty((int(dim),) + tuple(c.shape), dtype=torch.float32, device=c.device)
+    if not (_is_cuda_tensor(out) and out.dtype == torch.float32 and out.is_contiguous()
+            and out.numel() == int(dim) * nodes):
+        raise ValueError("out must be a contiguous float32 CUDA tensor of dim * nodes values")
+    L.check(L.lib().lbm_fade_apply_phi_noalloc(ctypes.byref(grid), ctypes.byref(P), ctypes.c_void_p(c.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
 
 
 def version() -> str:
