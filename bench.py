@@ -171,12 +171,14 @@ def measured_traffic():
         return None
 
 
-def profile_run(torch, LbmFade, synth, workload: str = WORKLOAD, reps: int = 20):
+def profile_run(torch, LbmFade, synth, workload: str = WORKLOAD, reps: int = 100):
     """Launch sequence for rocprofv3 (trace or counters): a plain 256 MiB copy
     (the calibration of FETCH_SIZE / WRITE_SIZE), then, per precision, `reps`
     launches of the fractional-term GEMM on the solver's own C and `reps`
     steps of the workload (the benchmark's by default; with its source, if it
-    has one)."""
+    has one).  The first GEMM launch of the process runs while the shader
+    clock is still ramping up (about 2.5x its later duration at 4096^2); with
+    100 launches it moves the trace's average by under 2 %."""
     a = torch.ones(64 * 1024 * 1024, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)

@@ -172,8 +172,7 @@ LBM_API int lbm_fade_set_f(lbm_fade_t h, const float* src, int32_t on_device, vo
  * Phi[mu*nodes + node] = p_mu I+(g_mu C) + (1-p_mu) I-(g_mu C) for every axis,
  * with the handle's precision.  C and Phi are host or device (same on_device).
  * C = NULL applies it to the solver's current concentration (device Phi only;
- * LBM_ESTATE before set_C/set_f): in split-BF16 mode this reuses the split the
- * last step produced, so the call is exactly the GEMM launch of a step.
+ * LBM_ESTATE before set_C/set_f): exactly the GEMM launch of a step.
  * Does not touch the solver state. */
 LBM_API int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t on_device, void* stream);
 
@@ -184,17 +183,17 @@ LBM_API int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t
  * generation, same kernels: the result equals lbm_fade_apply_phi on a handle
  * created with them, bit for bit).  C (nodes floats) and Phi (dim * nodes
  * floats, Phi[mu*nodes + node]) are device pointers on the current device,
- * ordered on `stream`; they are only borrowed.  The operator data and, with
- * LBM_BF16X3, the packed split of C are placed in a fixed device array of
- * LBM_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
- * runs on until the process ends: the call needs about 40 n bytes per axis of
- * n nodes (plus 4 bytes per node with LBM_BF16X3) and returns LBM_EINVAL,
- * naming the size, for a grid beyond that.  Every call on a device uses that
- * device's one array, so calls that overlap on one device (other host threads,
- * or other streams before this call's kernels have finished) race; calls
- * ordered on one stream are safe.  Synchronises `stream` once (after copying
- * the host-built operator data into the array); the fractional-term kernels
- * are then queued on `stream`. */
+ * ordered on `stream`; they are only borrowed.  The operator data (the
+ * Toeplitz generator, boundary columns and BF16 splits of every axis) are
+ * placed in a fixed device array of LBM_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds on every device it runs on until the process ends: the call
+ * needs about 40 n bytes per axis of n nodes and returns LBM_EINVAL, naming
+ * the size, for a grid beyond that.  Every call on a device uses that
+ * device's one array, so calls that overlap on one device (other host
+ * threads, or other streams before this call's kernels have finished) race;
+ * calls ordered on one stream are safe.  Synchronises `stream` once (after
+ * copying the host-built operator data into the array); the fractional-term
+ * kernels are then queued on `stream`. */
 #define LBM_NOALLOC_SCRATCH_BYTES (16u << 20)
 LBM_API int lbm_fade_apply_phi_noalloc(const lbm_grid* grid, const lbm_params* params, const float* C, float* Phi,
                                        void* stream);

@@ -689,7 +689,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
             }
             if (j + 1 < len)
                 ADJ_TRY(launch_collide_stream(h->cc, f_of(sg, b, j), A->seg_f[b] + (int64_t)(j + 1) * Q * nodes,
-                                              phi_j, h->S, A->seg_C[b] + (int64_t)(j + 1) * nodes, nullptr, st));
+                                              phi_j, h->S, A->seg_C[b] + (int64_t)(j + 1) * nodes, st));
         }
         return LBM_OK;
     };
@@ -722,7 +722,7 @@ int adjoint_run(lbm_fade* h, int64_t n, int ckpt_every, const float* gC, int on_
         int rc = recompute(sg, b, s);
         if (rc) return rc;
         ADJ_TRY(launch_collide_stream(h->cc, f_of(sg, b, len - 1), h->f[1 - h->cur],
-                                      A->seg_phi[b] + (int64_t)(len - 1) * d * nodes, h->S, h->C, h->Cp, s));
+                                      A->seg_phi[b] + (int64_t)(len - 1) * d * nodes, h->S, h->C, s));
         h->cur = 1 - h->cur;
         h->steps_done += len;
         h->at_initial_C = false;

@@ -4,8 +4,7 @@
 //
 // The operator data (Toeplitz generator, boundary columns and BF16 splits of
 // every axis, computed in FP64 on the host exactly as lbm_fade_create does)
-// and, in split-BF16 mode, the packed split of C live in one fixed device
-// array of the library.  Each device the library runs on holds its own copy
+// live in one fixed device array of the library.  Each device the library runs on holds its own copy
 // of the array at its own address; the address is looked up once per device
 // with hipGetSymbolAddress and only that pointer is handed to copies and
 // kernels (the array's name in host code is not a device address).
@@ -60,8 +59,7 @@ extern "C" int lbm_fade_apply_phi_noalloc(const lbm_grid* grid, const lbm_params
     if (rc) return rc;
     const int64_t nodes = (int64_t)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
     const size_t op_bytes = lbm::operator_image_bytes(*grid);
-    const size_t cp_off = (op_bytes + 255) & ~(size_t)255;
-    const size_t need = params->precision == LBM_BF16X3 ? cp_off + sizeof(uint32_t) * (size_t)nodes : op_bytes;
+    const size_t need = op_bytes;
     if (need > kScratchBytes)
         return fail(LBM_EINVAL, "grid too large for the no-allocation entry point: needs " + std::to_string(need) +
                                     " bytes of its " + std::to_string(kScratchBytes) + "-byte device scratch");
@@ -87,14 +85,7 @@ extern "C" int lbm_fade_apply_phi_noalloc(const lbm_grid* grid, const lbm_params
     e = hipMemcpyAsync(base, host.data(), op_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("upload of operator data: ") + hipGetErrorString(e));
-    const uint32_t* Cp = nullptr;
-    if (params->precision == LBM_BF16X3) {
-        uint32_t* packed = reinterpret_cast<uint32_t*>(base + cp_off);
-        e = lbm::launch_pack_bf16(C, packed, nodes, s);
-        if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("pack of C: ") + hipGetErrorString(e));
-        Cp = packed;
-    }
-    e = lbm::launch_fractional(ops, lays, grid->dim, params->precision, C, Cp, 0, Phi, nodes, s);
+    e = lbm::launch_fractional(ops, lays, grid->dim, params->precision, C, 0, Phi, nodes, s);
     if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("fractional term: ") + hipGetErrorString(e));
     return LBM_OK;
 }

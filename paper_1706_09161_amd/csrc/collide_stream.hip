@@ -84,20 +84,6 @@ __device__ __forceinline__ void stv(T* base, OFF boff, T v)
         *p = v;
 }
 
-// BF16 split of C for the split-BF16 fractional term: hi = bf16(c),
-// lo = bf16(c - hi), both round to nearest even, packed hi | lo << 16.
-__device__ __forceinline__ uint32_t bf16_bits(float x)
-{
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ uint32_t pack_hilo(float c)
-{
-    const uint32_t hi = bf16_bits(c);
-    const uint32_t lo = bf16_bits(c - __uint_as_float(hi << 16));
-    return hi | (lo << 16);
-}
-
 // Index of entry (a, b), a <= b, of a symmetric d x d block stored as its
 // upper triangle row by row: (00, 01, 11) in 2D, (00, 01, 02, 11, 12, 22) in 3D.
 __host__ __device__ constexpr int sym_index(int d, int a, int b) { return a * d - a * (a - 1) / 2 + (b - a); }
@@ -235,12 +221,11 @@ __device__ inline void collide_x_pair(const CollideConsts& cc, const float (&f)[
 // ---------------------------------------------------------------------------
 // 2D D2Q5 fused kernel.  Rows move through a ring of D slots: while row y + 1
 // is collided, the loads of rows y + 2 .. y + D are in flight.
-template <bool HAS_S, bool PACK, bool VAR, bool NT, typename OFF>
+template <bool HAS_S, bool VAR, bool NT, typename OFF>
 __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const float* __restrict__ fin,
                                                          float* __restrict__ fout, const float* __restrict__ Phi,
                                                          const float* __restrict__ S, float* __restrict__ Cout,
-                                                         uint32_t* __restrict__ Cpout, int rows_per_wave,
-                                                         int strips, int total_waves)
+                                                         int rows_per_wave, int strips, int total_waves)
 {
     constexpr int D = 4;
     const int nx = cc.n[0], ny = cc.n[1];
@@ -355,7 +340,6 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
                     c += f[i];
                 }
                 stv<NT>(Cout, b, c);
-                if (PACK) stv<NT>(Cpout, b, pack_hilo(c));
             }
             prev3 = cur[3];
 #pragma unroll
@@ -381,12 +365,11 @@ __global__ __launch_bounds__(256) void collide_stream_2d(CollideConsts cc, const
 // planes (the loads of planes z + 2 .. z + D are in flight while plane z + 1
 // is collided).  f*_3 / f*_4 cross rows through LDS, double-buffered by plane
 // parity so one barrier per plane suffices.
-template <int NY, bool HAS_S, bool PACK, bool VAR, bool NT, typename OFF>
+template <int NY, bool HAS_S, bool VAR, bool NT, typename OFF>
 __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, const float* __restrict__ fin,
                                                              float* __restrict__ fout, const float* __restrict__ Phi,
                                                              const float* __restrict__ S, float* __restrict__ Cout,
-                                                             uint32_t* __restrict__ Cpout, int planes_per_block,
-                                                             int strips_x, int strips_y)
+                                                             int planes_per_block, int strips_x, int strips_y)
 {
     // Two ring slots: the loads of plane z + 2 are in flight while plane z + 1
     // is collided.  Fewer registers than a deeper ring (86 against 110 VGPRs)
@@ -507,7 +490,6 @@ __global__ __launch_bounds__(64 * NY) void collide_stream_3d(CollideConsts cc, c
                     c += f[i];
                 }
                 stv<NT>(Cout, bo, c);
-                if (PACK) stv<NT>(Cpout, bo, pack_hilo(c));
             }
             prev5 = cur[5];
 #pragma unroll
@@ -584,11 +566,6 @@ __global__ void moment_kernel(const float* __restrict__ f, float* __restrict__ C
     C[x] = c;
 }
 
-__global__ void pack_kernel(const float* __restrict__ C, uint32_t* __restrict__ Cp, int64_t count)
-{
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < count) Cp[x] = pack_hilo(C[x]);
-}
 
 __global__ void nonfinite_kernel(const float* __restrict__ C, int64_t nodes, int* flag)
 {
@@ -618,13 +595,11 @@ void with_bool(bool v, F&& f)
         f(std::false_type{});
 }
 
-// f(integral_constant<bool, a>, ..., integral_constant<bool, d>)
+// f(integral_constant<bool, a>, integral_constant<bool, b>, integral_constant<bool, c>)
 template <typename F>
-void with_flags(bool a, bool b, bool c, bool d, F&& f)
+void with_flags(bool a, bool b, bool c, F&& f)
 {
-    with_bool(a, [&](auto A) {
-        with_bool(b, [&](auto B) { with_bool(c, [&](auto C) { with_bool(d, [&](auto D) { f(A, B, C, D); }); }); });
-    });
+    with_bool(a, [&](auto A) { with_bool(b, [&](auto B) { with_bool(c, [&](auto C) { f(A, B, C); }); }); });
 }
 
 // March length forced by LBM_COLLIDE_ROWS (tuning; 0 = automatic): rows per
@@ -639,7 +614,7 @@ int collide_rows_override()
 }  // namespace
 
 hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
-                                 const float* S, float* C_out, uint32_t* Cp_out, hipStream_t s)
+                                 const float* S, float* C_out, hipStream_t s)
 {
     // 32-bit byte offsets while every array (at most 7 fields of the node count) fits in 4 GiB
     const bool small = nodes_of(cc) * 7 * 4 < ((int64_t)1 << 32);
@@ -672,16 +647,15 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         const int waves = strips * chunks;
         const unsigned blocks = (unsigned)((waves + 3) / 4);
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out, rows,
-                               strips, waves);
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, cc, f_in, f_out, Phi, S, C_out, rows, strips,
+                               waves);
         };
-        with_flags(S != nullptr, Cp_out != nullptr, var, nt, [&](auto hs, auto pk, auto vr, auto ntc) {
-            constexpr bool HS = decltype(hs)::value, PK = decltype(pk)::value, VR = decltype(vr)::value,
-                           NT = decltype(ntc)::value;
+        with_flags(S != nullptr, var, nt, [&](auto hs, auto vr, auto ntc) {
+            constexpr bool HS = decltype(hs)::value, VR = decltype(vr)::value, NT = decltype(ntc)::value;
             if (small)
-                go(collide_stream_2d<HS, PK, VR, NT, uint32_t>);
+                go(collide_stream_2d<HS, VR, NT, uint32_t>);
             else
-                go(collide_stream_2d<HS, PK, VR, NT, uint64_t>);
+                go(collide_stream_2d<HS, VR, NT, uint64_t>);
         });
         return hipGetLastError();
     }
@@ -690,7 +664,7 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
     // neighbour on the same XCD has fetched.  At 256^3, 313 us against 322
     // with 16-row workgroups; the space-dependent variant (9 more values per
     // ring plane, up to 256 VGPRs) also needs the smaller workgroup.
-    auto launch3d = [&](auto ny_c, auto hs, auto pk, auto vr, auto ntc) {
+    auto launch3d = [&](auto ny_c, auto hs, auto vr, auto ntc) {
         constexpr int NY = decltype(ny_c)::value;
         const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
         const int sx = (nx + kStrip - 1) / kStrip;
@@ -708,27 +682,20 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         const int chunks = (nz + planes - 1) / planes;
         const int64_t blocks = (int64_t)sx * sy * chunks;
         if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-        constexpr bool HS = decltype(hs)::value, PK = decltype(pk)::value, VR = decltype(vr)::value,
-                       NT = decltype(ntc)::value;
-        auto kern =
-            small ? collide_stream_3d<NY, HS, PK, VR, NT, uint32_t> : collide_stream_3d<NY, HS, PK, VR, NT, uint64_t>;
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out, Phi, S, C_out, Cp_out,
-                           planes, sx, sy);
+        constexpr bool HS = decltype(hs)::value, VR = decltype(vr)::value, NT = decltype(ntc)::value;
+        auto kern = small ? collide_stream_3d<NY, HS, VR, NT, uint32_t> : collide_stream_3d<NY, HS, VR, NT, uint64_t>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NY), 0, s, cc, f_in, f_out, Phi, S, C_out, planes,
+                           sx, sy);
         return hipSuccess;
     };
     hipError_t e = hipSuccess;
-    with_flags(S != nullptr, Cp_out != nullptr, var, nt, [&](auto hs, auto pk, auto vr, auto ntc) {
-        e = launch3d(std::integral_constant<int, 8>{}, hs, pk, vr, ntc);
+    with_flags(S != nullptr, var, nt, [&](auto hs, auto vr, auto ntc) {
+        e = launch3d(std::integral_constant<int, 8>{}, hs, vr, ntc);
     });
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
-hipError_t launch_pack_bf16(const float* C, uint32_t* Cp, int64_t count, hipStream_t s)
-{
-    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, C, Cp, count);
-    return hipGetLastError();
-}
 
 hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f, hipStream_t s)
 {

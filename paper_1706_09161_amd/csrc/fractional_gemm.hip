@@ -448,7 +448,7 @@ hipError_t run_f32(FracLaunch& L, hipStream_t s)
 template <bool CONTIG, int NBJ, int WL, int KSPLIT, int P, bool KFULL>
 __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout& lay, const float* __restrict__ C,
                                               float* __restrict__ Phi, int tiles_l, int tiles_j, int bid, int total,
-                                              unsigned char* smem)
+                                              int lgroup, unsigned char* smem)
 {
     static_assert(WL * KSPLIT == kWaves, "4 wavefronts per workgroup");
     constexpr int JT = 32 * NBJ;  // outputs per tile
@@ -461,14 +461,18 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
     const int li = lane & 31, lh = lane >> 5;
 
     // tile of this workgroup: contiguous tile ranges per XCD; one-sided
-    // operators start their longest tiles first (see the split-BF16 kernel)
+    // operators start their longest tiles first (see the split-BF16 kernel),
+    // within groups of `lgroup` line tiles: the C panels of one group fit the
+    // XCD's L2 while all its output tiles run, so each panel is fetched once
     int lin = bid;
     if ((total & 7) == 0) {
         const int S = total >> 3, x = bid & 7, i = bid >> 3;
         lin = x * S + i;
         if ((op.lower_only || op.upper_only) && S % tiles_j == 0) {
-            const int lpx = S / tiles_j;
-            lin = x * S + (i % lpx) * tiles_j + i / lpx;
+            const int lpx = S / tiles_j;  // line tiles per XCD
+            const int G = (lgroup > 0 && lpx % lgroup == 0) ? lgroup : lpx;
+            const int per = G * tiles_j, g = i / per, r = i % per;
+            lin = x * S + (g * G + r % G) * tiles_j + r / G;
         }
     }
     int jt = lin % tiles_j;
@@ -751,10 +755,12 @@ __global__ __launch_bounds__(kThreads, 2) void fractional_f32_ring(FracLaunch L)
     const int total = L.first[axis + 1] - L.first[axis];
     if (L.lay[axis].contiguous)
         f32_ring_tile<true, NBJ, WL, KSPLIT, P, KFULL>(L.op[axis], L.lay[axis], L.C[axis], L.Phi[axis],
-                                                       L.tiles_m[axis], L.tiles_n[axis], local, total, smem_r);
+                                                       L.tiles_m[axis], L.tiles_n[axis], local, total, L.lgroup,
+                                                       smem_r);
     else
         f32_ring_tile<false, NBJ, WL, KSPLIT, P, KFULL>(L.op[axis], L.lay[axis], L.C[axis], L.Phi[axis],
-                                                        L.tiles_m[axis], L.tiles_n[axis], local, total, smem_r);
+                                                        L.tiles_m[axis], L.tiles_n[axis], local, total, L.lgroup,
+                                                        smem_r);
 }
 
 // tiles_m = line tiles (32 WL lines), tiles_n = output tiles (32 NBJ outputs)
@@ -788,6 +794,19 @@ hipError_t run_f32_ring(FracLaunch& L, hipStream_t s)
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     L.first[L.naxes] = (int)grid;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
+    // One-sided operators: groups of line tiles whose C panels (32 WL lines x
+    // n values each) fill at most the 4 MB L2 of an XCD.  At 4096^2 (8 tiles
+    // of 32 lines per group) the GEMM's L2 misses fall from 5.3x to 1.3x the
+    // C it needs, at the same speed (1107 / 1111 us; 4 tiles: 1.10x but
+    // 1125 us, 2 tiles: 1.51x, 1182 us).  LBM_FP32_LGROUP overrides (tuning).
+    {
+        int64_t nmax = 1;
+        for (int a = 0; a < L.naxes; ++a) nmax = L.op[a].n > nmax ? L.op[a].n : nmax;
+        int g = 1;
+        while (2 * g * (int64_t)(32 * WL) * nmax * 4 <= ((int64_t)4 << 20)) g *= 2;
+        L.lgroup = g;
+    }
+    if (const char* e = getenv("LBM_FP32_LGROUP")) L.lgroup = atoi(e);
     auto go = [&](auto kern) -> hipError_t {
         if (lds > 64 * 1024) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -810,7 +829,7 @@ hipError_t run_f32_auto(FracLaunch& L, hipStream_t s);
 }
 
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
-                             const uint32_t* Cp, int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s)
+                             int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s)
 {
     if (precision == 2) {
         for (int a = 0; a < naxes; ++a) {
@@ -832,13 +851,9 @@ hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxe
         L.op[a] = ops[a];
         L.lay[a] = lays[a];
         L.C[a] = C + a * in_stride;
-        L.Cp[a] = Cp ? Cp + a * in_stride : nullptr;
         L.Phi[a] = Phi + a * nodes;
     }
-    if (precision == 1) {
-        if (!Cp) return hipErrorInvalidValue;
-        return launch_fractional_bf16x3(L, s);
-    }
+    if (precision == 1) return launch_fractional_bf16x3(L, s);
     return run_f32_auto(L, s);
 }
 

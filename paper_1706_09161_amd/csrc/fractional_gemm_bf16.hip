@@ -5,11 +5,12 @@
 // Both operands are split into a high and a low BF16 part, x = x_hi + x_lo
 // with x_hi = bf16(x) and x_lo = bf16(x - x_hi) (round to nearest even):
 //   K C  ~  K_hi C_hi + K_hi C_lo + K_lo C_hi     (the K_lo C_lo term is dropped).
-// The Toeplitz weights are split on the host from their FP64 values; C is
-// split once per step by its producer (the collide-stream kernel, or a pack
-// kernel) into one packed word per node, which the staging only regroups.  Each dropped or rounded piece
-// is of relative size 2^-16 or below, against 2^-24 for FP32 operands, for a
-// 16 x (3 MFMA) rate advantage per product term over FP32 MFMA.
+// The Toeplitz weights are split on the host from their FP64 values; the
+// kernels read C in FP32 and split it as they load it (v_cvt_pk_bf16_f32, two
+// values per instruction), so no split copy of C is stored.  Each dropped or
+// rounded piece is of relative size 2^-16 or below, against 2^-24 for FP32
+// operands, for a 16 x (3 MFMA) rate advantage per product term over FP32
+// MFMA.
 //
 // Structure follows fractional_gemm.hip (same tiling, split-K, boundary-
 // column epilogue and one launch for all axes).  Operand convention for
@@ -32,15 +33,27 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 
+// BF16 split of two FP32 values of C: hi = bf16(c), lo = bf16(c - hi), both
+// rounded to nearest even by v_cvt_pk_bf16_f32 (c - hi is exact in FP32);
+// returned as the packed pairs hi0 | hi1 << 16 and lo0 | lo1 << 16.
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t& hp, uint32_t& lp)
+{
+    hp = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+    const float ra = a - __uint_as_float(hp << 16), rb = b - __uint_as_float(hp & 0xffff0000u);
+    lp = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{ra, rb}, bf16x2));
+}
+
 template <bool CONTIG, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int KSPLIT, int VEC>
 __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& lay, const float* __restrict__ C,
-                                            const uint32_t* __restrict__ Cp, float* __restrict__ Phi, int tiles_m,
-                                            int tiles_n, int bid, int total, unsigned char* smem)
+                                            float* __restrict__ Phi, int tiles_m, int tiles_n, int bid, int total,
+                                            unsigned char* smem)
 {
     static_assert(WAVES_M * WAVES_N * KSPLIT == kWaves, "4 wavefronts per workgroup");
     static_assert(BM == WAVES_M * 64 && BN == WAVES_N * 64, "64 x 64 per wavefront");
@@ -86,17 +99,16 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
 
     const int64_t lines = lay.lines;
     const float* Cb = C;
-    const uint32_t* Cpb = Cp;
     float* Pb = Phi;
     if (!CONTIG) {
         Cb += (int64_t)batch * lay.batch_stride;
-        Cpb += (int64_t)batch * lay.batch_stride;
         Pb += (int64_t)batch * lay.batch_stride;
     }
+    const uint32_t* Cbits = reinterpret_cast<const uint32_t*>(Cb);  // the FP32 values' bits
     const int64_t js = lay.j_stride;
 
-    // ---- staging: groups of 8 consecutive k of one line, read as packed
-    // (hi | lo << 16) words and regrouped into a hi and a lo BF16 row
+    // ---- staging: groups of 8 consecutive k of one line, read as FP32 and
+    // split into a hi and a lo BF16 row
     constexpr int GROUPS = CROWS * (BK / 8);
     constexpr int GPT = GROUPS / kThreads;
     static_assert(GROUPS % kThreads == 0, "tile not divisible");
@@ -112,8 +124,8 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                 const int k = k0 + 8 * g;
                 if constexpr (VEC == 4) {
                     if (line < lines && k + 7 < n) {
-                        const u32x4 v0 = *reinterpret_cast<const u32x4*>(Cpb + line * n + k);
-                        const u32x4 v1 = *reinterpret_cast<const u32x4*>(Cpb + line * n + k + 4);
+                        const u32x4 v0 = *reinterpret_cast<const u32x4*>(Cbits + line * n + k);
+                        const u32x4 v1 = *reinterpret_cast<const u32x4*>(Cbits + line * n + k + 4);
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             stage[q][e] = v0[e];
@@ -123,14 +135,14 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                     }
                 }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) stage[q][e] = (line < lines && k + e < n) ? Cpb[line * n + k + e] : 0u;
+                for (int e = 0; e < 8; ++e) stage[q][e] = (line < lines && k + e < n) ? Cbits[line * n + k + e] : 0u;
             } else {
                 const int row = id % BN, g = id / BN;
                 const int64_t line = (int64_t)n0 + row;
                 const int k = k0 + 8 * g;
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                    stage[q][e] = (line < lines && k + e < n) ? Cpb[(int64_t)(k + e) * js + line] : 0u;
+                    stage[q][e] = (line < lines && k + e < n) ? Cbits[(int64_t)(k + e) * js + line] : 0u;
             }
         }
     };
@@ -151,9 +163,10 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
             u32x4 hv, lv;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const uint32_t w0 = stage[q][2 * p], w1 = stage[q][2 * p + 1];
-                hv[p] = (w0 & 0xffffu) | (w1 << 16);
-                lv[p] = (w0 >> 16) | (w1 & 0xffff0000u);
+                uint32_t hp, lp;
+                split_pair(__uint_as_float(stage[q][2 * p]), __uint_as_float(stage[q][2 * p + 1]), hp, lp);
+                hv[p] = hp;
+                lv[p] = lp;
             }
             *reinterpret_cast<u32x4*>(hi + row * RS + 8 * g) = hv;
             *reinterpret_cast<u32x4*>(lo + row * RS + 8 * g) = lv;
@@ -312,11 +325,11 @@ __global__ __launch_bounds__(kThreads) void fractional_bf16x3_mfma(FracLaunch L)
     const int local = bid - L.first[axis];
     const int total = L.first[axis + 1] - L.first[axis];
     if (axis == 0)
-        bf16x3_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C[0], L.Cp[0], L.Phi[0],
+        bf16x3_tile<true, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, VEC_X>(L.op[0], L.lay[0], L.C[0], L.Phi[0],
                                                                        L.tiles_m[0],
                                                                        L.tiles_n[0], local, total, smem_b);
     else
-        bf16x3_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1>(L.op[axis], L.lay[axis], L.C[axis], L.Cp[axis],
+        bf16x3_tile<false, BM, BN, BK, WAVES_M, WAVES_N, KSPLIT, 1>(L.op[axis], L.lay[axis], L.C[axis],
                                                                     L.Phi[axis],
                                                                     L.tiles_m[axis], L.tiles_n[axis], local, total,
                                                                     smem_b);
@@ -370,10 +383,11 @@ hipError_t run_bf16(FracLaunch& L, hipStream_t s)
 // Register-ring kernel.  One wavefront computes 32 lines x (32 NBJ) outputs
 // of one axis over its share of k, in steps of 16 k:
 //  * the C fragment of a step (32 lines x 16 k) is loaded straight from the
-//    packed field into registers, P steps ahead (no LDS, no barrier in the
-//    k loop): along the contiguous axis a lane reads 8 consecutive packed
-//    words (two 16-byte loads), along a strided axis 8 words of one line at
-//    successive k, each load coalesced across the lanes (consecutive lines);
+//    FP32 field into registers, P steps ahead (no LDS, no barrier in the
+//    k loop), and split into its hi and lo BF16 planes there: along the
+//    contiguous axis a lane reads 8 consecutive values (two 16-byte loads),
+//    along a strided axis 8 values of one line at successive k, each load
+//    coalesced across the lanes (consecutive lines);
 //  * the Toeplitz fragment of output block c at step t equals that of block
 //    0 at step t - 2c (T(j + 32c - k) = T(j - (k - 32c))), so only the
 //    block-0 fragment of each new step is read; the last 2 NBJ of them stay
@@ -388,7 +402,7 @@ hipError_t run_bf16(FracLaunch& L, hipStream_t s)
 // are summed through LDS in a fixed order (deterministic).
 template <bool CONTIG, int NBJ, int WL, int KSPLIT, int P, bool VEC, bool KFULL>
 __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLayout& lay, const float* __restrict__ C,
-                                                 const uint32_t* __restrict__ Cp, float* __restrict__ Phi,
+                                                 float* __restrict__ Phi,
                                                  int tiles_l, int tiles_j, int bid, int total, unsigned char* smem)
 {
     static_assert(WL * KSPLIT == kWaves, "4 wavefronts per workgroup");
@@ -428,11 +442,9 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     const int64_t line0 = (int64_t)lt * LT + 32 * wl;
     const int64_t js = lay.j_stride;
     const float* Cb = C;
-    const uint32_t* Cpb = Cp;
     float* Pb = Phi;
     if (!CONTIG) {
         Cb += (int64_t)batch * lay.batch_stride;
-        Cpb += (int64_t)batch * lay.batch_stride;
         Pb += (int64_t)batch * lay.batch_stride;
     }
 
@@ -451,7 +463,9 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     // ---- C fragments: lane = (line li, k group lh).  Steps past the end of
     // the range re-read the last step, so every step issues the same loads.
     const int64_t my_line = min(line0 + li, lines - 1);  // rows past the end are computed, never stored
-    const uint32_t* q = CONTIG ? Cpb + my_line * n + kw + 8 * lh : Cpb + (int64_t)(kw + 8 * lh) * js + my_line;
+    // the FP32 field's bits, split into BF16 planes in registers
+    const uint32_t* Cw = reinterpret_cast<const uint32_t*>(Cb);
+    const uint32_t* q = CONTIG ? Cw + my_line * n + kw + 8 * lh : Cw + (int64_t)(kw + 8 * lh) * js + my_line;
     auto load_raw = [&](int t, uint32_t (&w)[8]) {
         const int tc = min(t, last);
         if constexpr (KFULL) {
@@ -474,7 +488,7 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
             const int k = kw + 16 * tc + 8 * lh;  // first k of this lane
             if constexpr (CONTIG && VEC) {
                 const bool ok = k < n;  // n % 8 == 0: all 8 values in range, or none
-                const uint32_t* a = ok ? q + 16 * tc : Cpb;
+                const uint32_t* a = ok ? q + 16 * tc : Cw;
                 const u32x4 v0 = *reinterpret_cast<const u32x4*>(a);
                 const u32x4 v1 = *reinterpret_cast<const u32x4*>(a + 4);
 #pragma unroll
@@ -488,7 +502,7 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const bool ok = k + e < n;
-                    const uint32_t v = *(ok ? a + e * stride : Cpb);
+                    const uint32_t v = *(ok ? a + e * stride : Cw);
                     w[e] = ok ? v : 0u;
                 }
             }
@@ -501,8 +515,10 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
         u32x4 h, l;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            h[p] = live ? __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x05040100u) : 0u;
-            l[p] = live ? __builtin_amdgcn_perm(w[2 * p + 1], w[2 * p], 0x07060302u) : 0u;
+            uint32_t hp, lp;
+            split_pair(__uint_as_float(w[2 * p]), __uint_as_float(w[2 * p + 1]), hp, lp);
+            h[p] = live ? hp : 0u;
+            l[p] = live ? lp : 0u;
         }
         hi = __builtin_bit_cast(bf16x8, h);
         lo = __builtin_bit_cast(bf16x8, l);
@@ -757,10 +773,10 @@ __global__ __launch_bounds__(kThreads, NBJ <= 4 ? 2 : 1) void fractional_bf16x3_
     const int local = bid - L.first[axis];
     const int total = L.first[axis + 1] - L.first[axis];
     if (axis == 0)
-        bf16x3_ring_tile<true, NBJ, WL, KSPLIT, P, VEC_X, KFULL>(L.op[0], L.lay[0], L.C[0], L.Cp[0], L.Phi[0], L.tiles_m[0],
+        bf16x3_ring_tile<true, NBJ, WL, KSPLIT, P, VEC_X, KFULL>(L.op[0], L.lay[0], L.C[0], L.Phi[0], L.tiles_m[0],
                                                           L.tiles_n[0], local, total, smem_r);
     else
-        bf16x3_ring_tile<false, NBJ, WL, KSPLIT, P, false, KFULL>(L.op[axis], L.lay[axis], L.C[axis], L.Cp[axis],
+        bf16x3_ring_tile<false, NBJ, WL, KSPLIT, P, false, KFULL>(L.op[axis], L.lay[axis], L.C[axis],
                                                            L.Phi[axis], L.tiles_m[axis], L.tiles_n[axis], local, total,
                                                            smem_r);
 }

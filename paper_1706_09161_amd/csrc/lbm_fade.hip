@@ -337,16 +337,7 @@ int check_device(lbm_fade* h)
 
 int run_phi(lbm_fade* h, const float* C, float* Phi, hipStream_t s)
 {
-    const uint32_t* Cp = nullptr;
-    if (h->params.precision == LBM_BF16X3) {
-        if (C == h->C) {
-            Cp = h->Cp;  // kept in sync by set_C / set_f / the collide-stream kernel
-        } else {
-            HIP_TRY(lbm::launch_pack_bf16(C, h->Cp_tmp, h->nodes, s));
-            Cp = h->Cp_tmp;
-        }
-    }
-    HIP_TRY(lbm::launch_fractional(h->ops, h->lays, h->dim, h->params.precision, C, Cp, 0, Phi, h->nodes, s));
+    HIP_TRY(lbm::launch_fractional(h->ops, h->lays, h->dim, h->params.precision, C, 0, Phi, h->nodes, s));
     return LBM_OK;
 }
 
@@ -354,7 +345,7 @@ int forward_step(lbm_fade* h, hipStream_t s)
 {
     int rc = run_phi(h, h->C, h->Phi, s);
     if (rc) return rc;
-    HIP_TRY(lbm::launch_collide_stream(h->cc, h->f[h->cur], h->f[1 - h->cur], h->Phi, h->S, h->C, h->Cp, s));
+    HIP_TRY(lbm::launch_collide_stream(h->cc, h->f[h->cur], h->f[1 - h->cur], h->Phi, h->S, h->C, s));
     h->cur = 1 - h->cur;
     h->steps_done += 1;
     h->at_initial_C = false;
@@ -424,11 +415,10 @@ int build_step_graph(lbm_fade* h)
     return LBM_OK;
 }
 
-// C := sum_i f_i of the current populations (and its BF16 split)
+// C := sum_i f_i of the current populations
 int refresh_C(lbm_fade* h, hipStream_t s)
 {
     HIP_TRY(lbm::launch_moment(h->cc, h->f[h->cur], h->C, s));
-    if (h->Cp) HIP_TRY(lbm::launch_pack_bf16(h->C, h->Cp, h->nodes, s));
     return LBM_OK;
 }
 
@@ -710,12 +700,6 @@ int lbm_fade_create(const lbm_grid* grid, int32_t lattice, const lbm_params* par
         cleanup();
         return fail(LBM_ENOMEM, "hipMalloc of the solver state failed");
     }
-    if (params->precision == LBM_BF16X3 &&
-        (hipMalloc(&h->Cp, sizeof(uint32_t) * h->nodes) != hipSuccess ||
-         hipMalloc(&h->Cp_tmp, sizeof(uint32_t) * h->nodes) != hipSuccess)) {
-        cleanup();
-        return fail(LBM_ENOMEM, "hipMalloc of the BF16 split of C failed");
-    }
     *out = h;
     g_error.clear();
     return LBM_OK;
@@ -735,8 +719,6 @@ void lbm_fade_destroy(lbm_fade_t h)
     (void)hipFree(h->S);
     (void)hipFree(h->dB);
     (void)hipFree(h->Cw);
-    (void)hipFree(h->Cp);
-    (void)hipFree(h->Cp_tmp);
     (void)hipFree(h->opmem);
     (void)hipFree(h->flag);
     delete h;
@@ -750,7 +732,6 @@ int lbm_fade_set_C(lbm_fade_t h, const float* C0, int32_t on_device, void* strea
     hipStream_t s = as_stream(stream);
     HIP_TRY(hipMemcpyAsync(h->C, C0, sizeof(float) * h->nodes, kind_to_dev(on_device), s));
     HIP_TRY(lbm::launch_wall_overwrite(h->cc, h->C, s));
-    if (h->Cp) HIP_TRY(lbm::launch_pack_bf16(h->C, h->Cp, h->nodes, s));
     rc = run_phi(h, h->C, h->Phi, s);
     if (rc) return rc;
     HIP_TRY(lbm::launch_equilibrium_init(h->cc, h->C, h->Phi, h->f[h->cur], s));
@@ -936,7 +917,7 @@ int lbm_fade_apply_phi(lbm_fade_t h, const float* C, float* Phi, int32_t on_devi
     if (rc) return rc;
     hipStream_t s = as_stream(stream);
     if (!C) {
-        // the solver's own concentration (and, in split-BF16 mode, its packed split)
+        // the solver's own concentration
         if (!h->has_state) return fail(LBM_ESTATE, "no state yet");
         if (!on_device) return fail(LBM_EINVAL, "C = NULL needs a device Phi");
         return run_phi(h, h->C, Phi, s);

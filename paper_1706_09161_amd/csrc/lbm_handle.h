@@ -22,8 +22,6 @@ struct lbm_fade {
     float* C = nullptr;
     float* Phi = nullptr;
     float* S = nullptr;
-    uint32_t* Cp = nullptr;       // split-BF16 path: packed BF16 split of C, kept in sync with C
-    uint32_t* Cp_tmp = nullptr;   // split-BF16 path: packed split of other inputs of the operator
     // space-dependent coefficients (allocated together on first use; cc.dB / cc.Cw
     // point at them while either is in use)
     float* dB = nullptr;          // d(d+1)/2 fields: lambda-bar(x)^-1 - lambda-bar^-1 (upper triangle)

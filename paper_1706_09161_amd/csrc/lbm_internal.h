@@ -65,10 +65,10 @@ struct FracLaunch {
     AxisLayout lay[kMaxOps];
     int tiles_m[kMaxOps], tiles_n[kMaxOps];
     int first[kMaxOps + 1];  // first workgroup id of every operator, first[naxes] = grid size
-    const float* C[kMaxOps];      // input field of every operator
-    const uint32_t* Cp[kMaxOps];  // the same fields split into BF16 (hi | lo << 16) (split-BF16 path)
+    const float* C[kMaxOps];  // input field of every operator
     float* Phi[kMaxOps];
     int naxes;  // operators in this launch
+    int lgroup;  // one-sided operators: line tiles per group of the tile order (0 = all of an XCD's)
 };
 
 // Constants of the fused collide-stream kernel (Sec. 2.2-2.5).
@@ -90,19 +90,16 @@ struct CollideConsts {
 
 // Kernel launchers (host functions).  All return a hipError_t.
 // Fractional term of all axes: axis a reads C + a * in_stride (in_stride = 0:
-// one field for every axis) and writes Phi + a * nodes.  The split-BF16 path
-// (precision 1) also reads Cp, the same fields packed by launch_pack_bf16.
+// one field for every axis) and writes Phi + a * nodes.
 hipError_t launch_fractional(const AxisOp* ops, const AxisLayout* lays, int naxes, int precision, const float* C,
-                             const uint32_t* Cp, int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s);
+                             int64_t in_stride, float* Phi, int64_t nodes, hipStream_t s);
 // FP32 only: nops (<= kMaxOps) operators with their own layouts, inputs and
 // outputs, in one launch.
 hipError_t launch_fractional_ops(const AxisOp* ops, const AxisLayout* lays, const float* const* C, float* const* Phi,
                                  int nops, hipStream_t s);
-// Cp[x] = bf16(C[x]) | bf16(C[x] - bf16(C[x])) << 16 (round to nearest even).
-hipError_t launch_pack_bf16(const float* C, uint32_t* Cp, int64_t count, hipStream_t s);
-// C_out receives the new moment; Cp_out (nullable) also its packed BF16 split.
+// C_out receives the new moment.
 hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, float* f_out, const float* Phi,
-                                 const float* S, float* C_out, uint32_t* Cp_out, hipStream_t s);
+                                 const float* S, float* C_out, hipStream_t s);
 hipError_t launch_equilibrium_init(const CollideConsts& cc, const float* C, const float* Phi, float* f,
                                    hipStream_t s);
 hipError_t launch_wall_overwrite(const CollideConsts& cc, float* C, hipStream_t s);

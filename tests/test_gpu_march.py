@@ -4,7 +4,7 @@ nodes are dealt out, never what a node computes: runs with the march forced
 through LBM_COLLIDE_ROWS to short, long, odd and grid-exceeding values give
 the populations and C of the default launch bit for bit, on ragged grids
 (partial 64-column strips, a last chunk shorter than the march), with and
-without a source, in FP32 and split-BF16 (which also writes the packed C) and
+without a source, in FP32 and split-BF16 and
 with the space-dependent fields.  The same holds for the non-temporal output
 stores that large grids use (forced here through LBM_COLLIDE_NT).
 """

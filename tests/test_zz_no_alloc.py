@@ -81,17 +81,20 @@ def test_noalloc_calls_queued_on_one_stream():
 
 
 def test_noalloc_rejects_grids_beyond_its_scratch():
-    """Sizes beyond the fixed scratch are refused with LBM_EINVAL before any
-    device work (host-side check), naming the sizes."""
+    """A grid whose operator data exceed the fixed scratch (about 40 bytes per
+    node of each axis) is refused with LBM_EINVAL before any device work
+    (host-side check), naming the sizes; a large grid within it runs."""
     from paper_1706_09161_amd import LbmError, _lib, apply_phi_noalloc
-
-    cfg = synth.small(2, [2100, 2100], seed=140)  # 4.4 M nodes: the BF16 split of C does not fit
-    Ct = torch.zeros((2100, 2100), device="cuda")
     from paper_1706_09161_amd.solver import config_kwargs
 
+    cfg = synth.small(2, [450000, 3], seed=140)  # ~18 MB of operator data along x
+    Ct = torch.zeros((3, 450000), device="cuda")
     with pytest.raises(LbmError) as ei:
-        apply_phi_noalloc(2, [2100, 2100], Ct, precision="bf16x3", **config_kwargs(cfg))
+        apply_phi_noalloc(2, [450000, 3], Ct, **config_kwargs(cfg))
     assert ei.value.code == _lib.LBM_EINVAL and "scratch" in str(ei.value)
-    out = apply_phi_noalloc(2, [2100, 2100], Ct, precision="fp32", **config_kwargs(cfg))  # FP32 fits
-    torch.cuda.synchronize()
-    assert not torch.any(out).item()
+    cfg = synth.small(2, [2100, 2100], seed=141)
+    Ct = torch.zeros((2100, 2100), device="cuda")
+    for precision in ("fp32", "bf16x3"):
+        out = apply_phi_noalloc(2, [2100, 2100], Ct, precision=precision, **config_kwargs(cfg))
+        torch.cuda.synchronize()
+        assert not torch.any(out).item()
