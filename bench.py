@@ -220,6 +220,31 @@ def profile_adjoint(torch, LbmFade, synth):
     log("adjoint profile run done")
 
 
+def copy_ceiling(torch, nbytes: float, repeats: int = 5) -> dict:
+    """Reference for the HBM-bound kernels: a plain device-to-device copy
+    (torch's copy kernel) that reads and writes nbytes / 2 each, the traffic
+    of one collide-stream launch; median of `repeats` timed copies after one
+    untimed one."""
+    n = int(nbytes / 2 / 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    stream = torch.cuda.current_stream()
+    for _ in range(repeats):
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        st.record(stream)
+        b.copy_(a)
+        en.record(stream)
+        torch.cuda.synchronize()
+        ts.append(st.elapsed_time(en) / 1e3)
+    sec = float(np.median(ts))
+    del a, b
+    return {"bytes_moved": 2 * 4 * n, "us": sec * 1e6, "GBps": 2 * 4 * n / sec / 1e9,
+            "what": "torch device copy of the same traffic (half read, half written)"}
+
+
 def adjoint_ratio(torch, LbmFade, synth, repeats: int = 3):
     """Wall time of lbm_fade_adjoint(500 steps, checkpoint every 50) over that of
     500 forward steps on the 512^2 adjoint workload (misfit gradient point);
@@ -417,6 +442,10 @@ def main():
                      "flops_per_launch": flops, "avg_us_per_launch": r["gemm_s"] * 1e6,
                      "algorithmic_bytes_per_launch": gemm_bytes_per_step(cfg)},
         "fp32_detail": head["fp32"],
+        "collide_stream": {"bound": "hbm", "algorithmic_bytes_per_step": collide_bytes_per_step(cfg),
+                           "us_fp32_step_minus_gemm": head["fp32"]["collide_us_step_minus_gemm"],
+                           "GBps": head["fp32"]["collide_GBps_step_minus_gemm"], "peak_GBps": PEAK["hbm_GBps"],
+                           "copy_reference": copy_ceiling(torch, collide_bytes_per_step(cfg))},
     }
     if not args.no_secondary:
         line["secondary"] = {}

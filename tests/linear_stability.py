@@ -33,22 +33,36 @@ def symbol(theta: float, alpha: float, p: float, dx: float, K: int = 4000) -> co
 
 
 def spectral_radius(u_lat: float, lam: float, tau_free: float, alpha: float, p: float, dx: float, bgk: bool,
-                    nk: int = 181) -> float:
+                    nk: int = 181, tau4: float | None = None, free_as_rates: bool = False,
+                    velocity_squared: bool = False, ky_step: int | None = None) -> float:
     """Largest |eigenvalue| of G over a grid of wave vectors (k_x, k_y) in
     [-pi, pi]^2, velocity (u_lat, 0) in lattice units, isotropic
-    relaxation time lam of the fluxes (BGK: of every moment)."""
+    relaxation time lam of the fluxes (BGK: of every moment).
+
+    Alternative readings of Sec. 3.3, for comparison with the printed scheme
+    (the defaults): tau4 gives row 4 of M (0, 1, 1, -1, -1) its own value
+    (tau_free then belongs to row 3 only); free_as_rates takes the free values
+    as relaxation rates (Lambda's entries) instead of times; velocity_squared
+    adds the second-order velocity terms of the usual advection-diffusion
+    equilibrium, w_i C [(e_i.u)^2 / (2 e^4) - u^2 / (2 e^2)], which equation
+    (Feq) does not have."""
+    t3 = tau_free
+    t4 = tau_free if tau4 is None else tau4
     if bgk:
         R = np.eye(5) / lam
+    elif free_as_rates:
+        R = np.linalg.inv(M) @ np.diag([1.0, 1 / lam, 1 / lam, t3, t4]) @ M
     else:
-        R = np.linalg.inv(M) @ np.diag([1.0, 1 / lam, 1 / lam, 1 / tau_free, 1 / tau_free]) @ M
+        R = np.linalg.inv(M) @ np.diag([1.0, 1 / lam, 1 / lam, 1 / t3, 1 / t4]) @ M
     ks = np.linspace(-math.pi, math.pi, nk)
     sym = {k: symbol(k, alpha, p, dx) for k in ks}
+    u2 = W * ((E_VEC[:, 0] * u_lat) ** 2 / (2 * E2 * E2) - u_lat ** 2 / (2 * E2)) if velocity_squared else 0.0
     best = 0.0
     for kx in ks:
-        for ky in ks[:: max(1, nk // 30)]:
+        for ky in ks[:: (ky_step or max(1, nk // 30))]:
             px, py = sym[kx], sym[ky]
             feq = np.array([1 - W[0] * (px + py), W[1] * (px + u_lat / E2), W[2] * (px - u_lat / E2), W[3] * py,
-                            W[4] * py])
+                            W[4] * py]) + u2
             A = np.eye(5) - R + R @ np.outer(feq, np.ones(5))
             S = np.diag(np.exp(-1j * (E_VEC[:, 0] * kx + E_VEC[:, 1] * ky)))
             best = max(best, float(np.abs(np.linalg.eigvals(S @ A)).max()))

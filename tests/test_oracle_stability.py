@@ -69,3 +69,31 @@ def test_larger_free_times_grow_more_slowly():
         r_bgk = spectral_radius(u1 * dt / dx, 0.548, 1.0, alpha, 0.5, dx, True, nk=91)
         r = [spectral_radius(u1 * dt / dx, 0.548, t, alpha, 0.5, dx, False, nk=91) for t in (1.0, 2.1277, 2.6316)]
         assert r_bgk > r[0] > r[1] > r[2] >= 1.0, (alpha, u1, r_bgk, r)
+
+
+def test_alternative_readings_of_section_3_3():
+    """Sec. 3.3 states that free relaxation times lambda_3 = lambda_4 > 0.833
+    re-stabilise the advection-diffusion case at u1 = 5, and that 2.1277 and
+    2.6316 keep alpha = 1.7 stable at u1 = 1 and 1.3.  No reading of the
+    scheme tried here reproduces all of these (von Neumann radii; the scheme
+    as printed is the default reading):
+      * as printed: 0.833 grows (radius 1.125), 2.1277 / 2.6316 grow by ~1 %;
+      * one free time on row 3 or row 4 of M only (the other 1): still grows,
+        so the garbled D2Q5 mapping of lambda_3 / lambda_4 does not matter;
+      * free values as rates (Lambda's entries): rates above 2 diverge;
+      * the usual second-order velocity terms in f^eq (not in eq. (Feq)): 0.833
+        becomes stable for the advection-diffusion case but 1.0 and 2.1277
+        do not (the opposite of '> 0.833'), and alpha = 1.7 still grows."""
+    dx, dt, lam = 0.01, 8e-4, 0.548
+    kw = dict(nk=61, ky_step=1)
+    u5, u1 = 5.0 * dt / dx, 1.0 * dt / dx
+    printed = spectral_radius(u5, lam, 0.833, 2.0, 0.5, dx, False, **kw)
+    assert printed > 1.1
+    assert spectral_radius(u5, lam, 10.0, 2.0, 0.5, dx, False, **kw) <= 1.0 + 1e-9
+    assert spectral_radius(u5, lam, 0.833, 2.0, 0.5, dx, False, tau4=1.0, **kw) > 1.1
+    assert spectral_radius(u5, lam, 1.0, 2.0, 0.5, dx, False, tau4=0.833, **kw) > 1.1
+    assert spectral_radius(u1, lam, 2.1277, 1.7, 0.5, dx, False, free_as_rates=True, **kw) > 1.2
+    assert spectral_radius(u5, lam, 0.833, 2.0, 0.5, dx, False, velocity_squared=True, **kw) <= 1.0 + 1e-9
+    assert spectral_radius(u5, lam, 1.0, 2.0, 0.5, dx, False, velocity_squared=True, **kw) > 1.002
+    assert spectral_radius(u1, lam, 2.1277, 1.7, 0.5, dx, False, velocity_squared=True, **kw) > 1.005
+    assert spectral_radius(u1, lam, 2.1277, 1.7, 0.5, dx, False, **kw) > 1.005
