@@ -483,7 +483,9 @@ bool build_ops(lbm_fade* h, AdjointState* A)
             gU[dd + N] = dd <= 0 ? (float)(s * C.a[-dd]) : 0.f;
             gL[dd + N] = dd >= 0 ? (float)(s * C.a[dd]) : 0.f;
         }
-        // d(corr0)/dp and d(corrN)/dp of the forward operator (make_axis_weights)
+        // p-derivatives of the boundary corrections K[j][0] - T(j) and
+        // K[j][N] - T(j - N) (the transposed Toeplitz parts U and L span every
+        // column, the end columns included)
         {
             const double gm = 2.0 - h->params.alpha[mu];
             const double empty = pow(0.0, gm);  // c+_{00} = c-_{NN}
@@ -508,8 +510,9 @@ bool build_ops(lbm_fade* h, AdjointState* A)
         U.n = n;
         U.lower_only = 0;
         U.upper_only = 1;
+        U.ends_excluded = 0;
         U.gen = reinterpret_cast<const float*>(base + oU);
-        U.corr0 = U.corrN = zeros;
+        U.col0 = U.colN = zeros;
         U.gen_hi = U.gen_lo = nullptr;
         U.pw_hi = U.pw_lo = nullptr;
         AxisOp& L = A->opsL[mu];

@@ -5,12 +5,14 @@
 //   K[j][k] = g dx^gamma / Gamma(2+gamma) * (p c+_{kj}(gamma) + (1-p) c-_{kj}(gamma, N))
 // (Sec. 2.4, equations (1Dminus_discret), (c+), (c-), (XXminus_discret)),
 // which is Toeplitz except in its first and last columns:
-//   K[j][k] = T(j - k) + [k == 0] corr0[j] + [k == N] corrN[j].
+//   K[j][k] = T(j - k) for 0 < k < N,  K[j][0] = col0[j],  K[j][N] = colN[j].
 // So Phi = K C for all lines at once is a dense contraction (n x n times
-// n x lines).  It runs as a GEMM on the matrix cores; the Toeplitz operand is
-// never stored as an n x n matrix: each workgroup keeps the 2n-1 generator
-// values it needs in LDS and reads fragments from there, and the two boundary
-// columns are a rank-2 epilogue.
+// n x lines).  It runs as a GEMM on the matrix cores over the interior columns
+// (the end columns' C values are zeroed as they are loaded); the Toeplitz
+// operand is never stored as an n x n matrix: each workgroup keeps the 2n-1
+// generator values it needs in LDS and reads fragments from there, and the
+// two boundary columns are a rank-2 epilogue.  (The adjoint's transposed
+// parts, ends_excluded = 0, sum every column and add col0 / colN on top.)
 //
 // Layouts (see AxisLayout):
 //   x axis  ("contiguous"): D[line][j]      = sum_k C[line][k] T(j - k)
@@ -46,14 +48,15 @@ __global__ __launch_bounds__(256) void fractional_simt(AxisOp op, AxisLayout lay
     int64_t total = lay.contiguous ? lay.lines * n : (int64_t)lay.batches * n * lay.lines;
     if (t >= total) return;
     const float* gen = op.gen + (n - 1);
+    const int k_lo = op.ends_excluded ? 1 : 0, k_hi = op.ends_excluded ? N : n;  // Toeplitz columns summed
     if (lay.contiguous) {
         const int64_t line = t / n;
         const int j = (int)(t % n);
         const float* c = C + line * n;
         float acc = 0.f;
-        for (int k = 0; k < n; ++k) acc = fmaf(gen[j - k], c[k], acc);
-        acc = fmaf(op.corr0[j], c[0], acc);
-        acc = fmaf(op.corrN[j], c[N], acc);
+        for (int k = k_lo; k < k_hi; ++k) acc = fmaf(gen[j - k], c[k], acc);
+        acc = fmaf(op.col0[j], c[0], acc);
+        acc = fmaf(op.colN[j], c[N], acc);
         Phi[line * n + j] = acc;
     } else {
         const int64_t line = t % lay.lines;
@@ -62,9 +65,9 @@ __global__ __launch_bounds__(256) void fractional_simt(AxisOp op, AxisLayout lay
         const int64_t b = rest / n;
         const float* c = C + b * lay.batch_stride + line;
         float acc = 0.f;
-        for (int k = 0; k < n; ++k) acc = fmaf(gen[j - k], c[(int64_t)k * lay.j_stride], acc);
-        acc = fmaf(op.corr0[j], c[0], acc);
-        acc = fmaf(op.corrN[j], c[(int64_t)N * lay.j_stride], acc);
+        for (int k = k_lo; k < k_hi; ++k) acc = fmaf(gen[j - k], c[(int64_t)k * lay.j_stride], acc);
+        acc = fmaf(op.col0[j], c[0], acc);
+        acc = fmaf(op.colN[j], c[(int64_t)N * lay.j_stride], acc);
         Phi[b * lay.batch_stride + (int64_t)j * lay.j_stride + line] = acc;
     }
 }
@@ -217,6 +220,27 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
             }
         }
     };
+    // forward operators leave columns k = 0 and k = N out of the Toeplitz sum
+    // (the epilogue adds the whole boundary columns): zero them in the staged
+    // chunk that holds them
+    auto mask_ends = [&](int k0) {
+        if (!op.ends_excluded || (k0 > 0 && k0 + BK <= N)) return;
+#pragma unroll
+        for (int q = 0; q < PER_THREAD; ++q) {
+            const int e = (q * kThreads + threadIdx.x) * VEC;
+            if constexpr (CONTIG) {
+                const int k = k0 + e % BK;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v)
+                    if (k + v == 0 || k + v == N) stage[q][v] = 0.f;
+            } else {
+                const int k = k0 + e / BN;
+                if (k == 0 || k == N)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) stage[q][v] = 0.f;
+            }
+        }
+    };
     auto store_tile = [&](float* tile) {
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
@@ -249,6 +273,7 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
     const int rowA = (CONTIG ? 0 : m0) + wm * 64;  // first Toeplitz row / C-tile row of this wavefront
     const int colB = (CONTIG ? n0 : 0) + wn * 64;
     load_tile(kb);
+    mask_ends(kb);  // the first chunk is consumed right away
     store_tile(tile0);
     __syncthreads();
 
@@ -290,7 +315,10 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st % 3][i], b[st % 3][j], acc[i][j], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (t + 1 < nk) store_tile(nxt);
+        if (t + 1 < nk) {
+            mask_ends(k0 + BK);  // where the prefetched chunk is consumed
+            store_tile(nxt);
+        }
         __syncthreads();
     }
 
@@ -342,8 +370,8 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
                     if (line < lines && jj < n) {
                         const float* c = Cb + line * n;
                         float v = acc[i][j][r];
-                        v = fmaf(op.corr0[jj], c[0], v);
-                        v = fmaf(op.corrN[jj], c[N], v);
+                        v = fmaf(op.col0[jj], c[0], v);
+                        v = fmaf(op.colN[jj], c[N], v);
                         Pb[line * n + jj] = v;
                     }
                 } else {
@@ -351,8 +379,8 @@ __device__ __forceinline__ void fractional_tile(const AxisOp& op, const AxisLayo
                     const int64_t line = nn;
                     if (jj < n && line < lines) {
                         float v = acc[i][j][r];
-                        v = fmaf(op.corr0[jj], Cb[line], v);
-                        v = fmaf(op.corrN[jj], Cb[(int64_t)N * js + line], v);
+                        v = fmaf(op.col0[jj], Cb[line], v);
+                        v = fmaf(op.colN[jj], Cb[(int64_t)N * js + line], v);
                         Pb[(int64_t)jj * js + line] = v;
                     }
                 }
@@ -506,6 +534,7 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
     // C of a group: lane = (line li, k half lh), 4 consecutive k
     const int64_t my_line = min(line0 + li, lines - 1);  // rows past the end are computed, never stored
     const float* q = CONTIG ? Cb + my_line * n + kw + 4 * lh : Cb + (int64_t)(kw + 4 * lh) * js + my_line;
+    const bool ends = op.ends_excluded != 0;
     auto load_c = [&](int g, f32x4& v) {
         const int gc = min(g, last);
         if constexpr (KFULL) {
@@ -528,8 +557,29 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
             }
         }
     };
+    // Forward operators leave columns k = 0 and k = N out of the Toeplitz sum
+    // (the epilogue adds the whole boundary columns).  k ranges start at
+    // multiples of 8, so k = 0 is element 0 of lane half 0 in group 0 of the
+    // wavefront that starts at 0 (zeroed once, before the loop), and k = N is
+    // element N % 4 of lane half (N % 8) / 4 in the one group holding it;
+    // with n % 8 == 0 that element is always the last.  It is zeroed with a
+    // select where the group is consumed (no branch: the interleaved MFMA /
+    // load block of a group stays one block).
+    const bool lane_k0 = ends && kw == 0 && lh == 0;
+    const bool lane_kN = ends && lh == (N % 8) / 4;
+    const int g_kN = (ends && N >= kw && N < kw + 8 * my_groups) ? (N - kw) / 8 : -1;
+    auto kill_kN = [&](int g, f32x4& v) {
+        const bool kn = lane_kN && g == g_kN;
+        if constexpr (KFULL) {
+            v[3] = kn ? 0.f : v[3];
+        } else {
+            const int e_kN = N % 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (kn && e == e_kN) ? 0.f : v[e];
+        }
+    };
 
-    // LDS: corr0 | corrN | C at the walls of each line (contiguous axis) |
+    // LDS: col0 | colN | C at the walls of each line (contiguous axis) |
     // Toeplitz window, d decreasing (later the k-share reduction)
     float* c0s = reinterpret_cast<float*>(smem);
     float* cNs = c0s + JT;
@@ -561,8 +611,8 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
     {
         const int t = threadIdx.x;
         if (t < JT && j0 + t < n) {
-            cv0 = op.corr0[j0 + t];
-            cvN = op.corrN[j0 + t];
+            cv0 = op.col0[j0 + t];
+            cvN = op.colN[j0 + t];
         }
         if (CONTIG && t < LT) {
             const int64_t line = min((int64_t)lt * LT + t, lines - 1);
@@ -595,6 +645,7 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
         fill_store(base, fv);
     }
     lds_barrier();  // the C prefetch stays in flight
+    craw[0][0] = lane_k0 ? 0.f : craw[0][0];  // k = 0 is only ever in group 0
 
     f32x16 acc[NBJ];
 #pragma unroll
@@ -623,6 +674,7 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
                 // C of this group (zero past the end of the range), then reuse its slot for group g + P
                 f32x4 cur = craw[u % P];
                 if (g >= my_groups) cur = f32x4{0.f, 0.f, 0.f, 0.f};
+                kill_kN(g, cur);
                 load_c(g + P, craw[u % P]);
                 load_t(g + 1, tf[(u + 1) & 1]);
 #pragma unroll

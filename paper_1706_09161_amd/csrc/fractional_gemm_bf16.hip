@@ -146,6 +146,21 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
             }
         }
     };
+    // forward operators leave columns k = 0 and k = N out of the Toeplitz sum
+    // (the epilogue adds the whole boundary columns): zero them in the staged
+    // chunk that holds them
+    auto mask_ends = [&](int k0) {
+        if (!op.ends_excluded || (k0 > 0 && k0 + BK <= N)) return;
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) {
+            const int id = q * kThreads + threadIdx.x;
+            const int g = CONTIG ? id % (BK / 8) : id / BN;
+            const int k = k0 + 8 * g;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (k + e == 0 || k + e == N) stage[q][e] = 0u;
+        }
+    };
     auto store_tile = [&](int buf) {
         uint16_t* hi = ctile + (2 * buf) * CT;
         uint16_t* lo = ctile + (2 * buf + 1) * CT;
@@ -186,6 +201,7 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
     const int toepBase = (CONTIG ? n0 + wn * 64 : m0 + wm * 64);
     const int ctBase = (CONTIG ? wm * 64 : wn * 64);
     load_tile(kb);
+    mask_ends(kb);  // the first chunk is consumed right away
     store_tile(0);
     __syncthreads();
 
@@ -250,7 +266,10 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                     }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (t + 1 < nk) store_tile(buf ^ 1);
+        if (t + 1 < nk) {
+            mask_ends(k0 + BK);  // where the prefetched chunk is consumed
+            store_tile(buf ^ 1);
+        }
         __syncthreads();
     }
 
@@ -297,8 +316,8 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                     if (line < lines && jj < n) {
                         const float* c = Cb + line * n;
                         float v = acc[i][j][r];
-                        v = fmaf(op.corr0[jj], c[0], v);
-                        v = fmaf(op.corrN[jj], c[N], v);
+                        v = fmaf(op.col0[jj], c[0], v);
+                        v = fmaf(op.colN[jj], c[N], v);
                         Pb[line * n + jj] = v;
                     }
                 } else {
@@ -306,8 +325,8 @@ __device__ __forceinline__ void bf16x3_tile(const AxisOp& op, const AxisLayout& 
                     const int64_t line = nn;
                     if (jj < n && line < lines) {
                         float v = acc[i][j][r];
-                        v = fmaf(op.corr0[jj], Cb[line], v);
-                        v = fmaf(op.corrN[jj], Cb[(int64_t)N * js + line], v);
+                        v = fmaf(op.col0[jj], Cb[line], v);
+                        v = fmaf(op.colN[jj], Cb[(int64_t)N * js + line], v);
                         Pb[(int64_t)jj * js + line] = v;
                     }
                 }
@@ -466,6 +485,7 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     // the FP32 field's bits, split into BF16 planes in registers
     const uint32_t* Cw = reinterpret_cast<const uint32_t*>(Cb);
     const uint32_t* q = CONTIG ? Cw + my_line * n + kw + 8 * lh : Cw + (int64_t)(kw + 8 * lh) * js + my_line;
+    const bool ends = op.ends_excluded != 0;
     auto load_raw = [&](int t, uint32_t (&w)[8]) {
         const int tc = min(t, last);
         if constexpr (KFULL) {
@@ -508,6 +528,27 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
             }
         }
     };
+    // Forward operators leave columns k = 0 and k = N out of the Toeplitz sum
+    // (the epilogue adds the whole boundary columns).  k ranges start at
+    // multiples of 16, so k = 0 is element 0 of lane half 0 in step 0 of the
+    // wavefront that starts at 0, and k = N is element N % 8 of lane half
+    // (N % 16) / 8 in the one step holding it; with n % 8 == 0 that element
+    // is always the last.  Their C values are zeroed with selects before the
+    // step is split (no branch: the interleaved MFMA / load block of the loop
+    // body stays one block).
+    const bool lane_k0 = ends && kw == 0 && lh == 0;
+    const bool lane_kN = ends && lh == (N % 16) / 8;
+    const int t_kN = (ends && N >= kw && N < kw + 16 * my_steps) ? (N - kw) / 16 : -1;
+    auto kill_kN = [&](int t, uint32_t (&w)[8]) {
+        const bool kn = lane_kN && t == t_kN;
+        if constexpr (KFULL || VEC) {
+            w[7] = kn ? 0u : w[7];
+        } else {
+            const int e_kN = N % 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w[e] = (kn && e == e_kN) ? 0u : w[e];
+        }
+    };
     // BF16 hi and lo planes of a C fragment; zero for steps past the end of
     // this wavefront's range (their products then add nothing, so every step
     // runs the same straight-line code)
@@ -523,7 +564,7 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
         hi = __builtin_bit_cast(bf16x8, h);
         lo = __builtin_bit_cast(bf16x8, l);
     };
-    // ---- LDS: corr0 | corrN | C at the two walls of each line (contiguous
+    // ---- LDS: col0 | colN | C at the two walls of each line (contiguous
     // axis) | pair-word window hi | lo (later the k-share reduction)
     float* c0s = reinterpret_cast<float*>(smem);
     float* cNs = c0s + JT;
@@ -567,8 +608,8 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
     {
         const int t = threadIdx.x;  // JT <= kThreads
         if (t < JT && j0 + t < n) {
-            cv0 = op.corr0[j0 + t];
-            cvN = op.corrN[j0 + t];
+            cv0 = op.col0[j0 + t];
+            cvN = op.colN[j0 + t];
         }
         if (CONTIG && t < LT) {
             const int64_t line = min((int64_t)lt * LT + t, lines - 1);
@@ -629,15 +670,20 @@ __device__ __forceinline__ void bf16x3_ring_tile(const AxisOp& op, const AxisLay
         // ring slots of steps -R+2 .. 0 (blocks c >= 1 of the first steps)
 #pragma unroll
         for (int t = -(R - 2); t <= 0; ++t) load_t(t, th[(t + R) % R], tl[(t + R) % R]);
+        raw[0][0] = lane_k0 ? 0u : raw[0][0];  // k = 0 is only ever in step 0
+        kill_kN(0, raw[0]);
         cvt(raw[0], true, ch[0], cl[0]);
 
         for (int t0 = 0; t0 < my_steps; t0 += R) {
 #pragma unroll
             for (int u = 0; u < R; ++u) {
                 const int t = t0 + u;
-                // prefetch: Toeplitz fragment of step t + 1, C of step t + P (slot of step t, converted already)
+                // prefetch the Toeplitz fragment of step t + 1 and the C of step
+                // t + P (into the slot of step t, converted already), then split
+                // the C of step t + 1 (its column N zeroed first)
                 load_t(t + 1, th[(u + 1) % R], tl[(u + 1) % R]);
                 load_raw(t + P, raw[u % P]);
+                kill_kN(t + 1, raw[(u + 1) % P]);
                 cvt(raw[(u + 1) % P], t + 1 < my_steps, ch[(u + 1) & 1], cl[(u + 1) & 1]);
                 const bf16x8 chh = ch[u & 1], cll = cl[u & 1];
 #pragma unroll

@@ -167,18 +167,24 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Forward operator of one axis from the product-rule coefficients:
-// K[j][k] = s (p c+_{kj} + (1-p) c-_{kj}) = T(j - k) + [k == 0] corr0[j] + [k == N] corrN[j].
-// The integrals over the empty intervals (c+_{00}, c-_{NN}) are 0^gamma: the
-// value that keeps constants integrated exactly at j = 0 and j = N.
+// K[j][k] = s (p c+_{kj} + (1-p) c-_{kj}), Toeplitz in its interior columns,
+// K[j][k] = T(j - k) for 0 < k < N, and two boundary columns col0[j] = K[j][0],
+// colN[j] = K[j][N]:
+//   K[j][0] = s p c+_{0j} (j >= 1),  K[0][0] = s (p 0^gamma + (1 - p)),
+//   K[j][N] = s (1-p) c-_{Nj} (j <= N-1),  K[N][N] = s (p + (1 - p) 0^gamma)
+// (c-_{0j} and c+_{Nj} vanish off the diagonal; the diagonal entries that are
+// not empty-interval integrals are 1).  The integrals over the empty
+// intervals (c+_{00}, c-_{NN}) are 0^gamma: the value that keeps constants
+// integrated exactly at j = 0 and j = N.
 // flux_form 1 (the Caputo-type flux (Fg2) of Sec. 3.5): integration by parts
 // (equations (PSRLdD-a), (PSRLdD-b), (CoeffA_FADE3DPS)) subtracts
 // g C(x_0) (j dx)^gamma / Gamma(1 + gamma) (times p) and
 // g C(x_N) ((N - j) dx)^gamma / Gamma(1 + gamma) (times 1 - p), a change of the
 // two boundary columns only: s (1 + gamma) j^gamma in units of s.
 struct AxisWeights {
-    std::vector<double> T;      // T(d) at d + N, d in [-N, N]
-    std::vector<double> corr0;  // n
-    std::vector<double> corrN;  // n
+    std::vector<double> T;     // T(d) at d + N, d in [-N, N]
+    std::vector<double> col0;  // n: K[j][0]
+    std::vector<double> colN;  // n: K[j][N]
 };
 
 AxisWeights make_axis_weights(int n, double gamma, double p, double g, double dx, int flux_form)
@@ -188,8 +194,8 @@ AxisWeights make_axis_weights(int n, double gamma, double p, double g, double dx
     const double s = A.s;
     AxisWeights W;
     W.T.assign(2 * N + 1, 0.0);
-    W.corr0.assign(n, 0.0);
-    W.corrN.assign(n, 0.0);
+    W.col0.assign(n, 0.0);
+    W.colN.assign(n, 0.0);
     for (int d = -N; d <= N; ++d) {
         double v;
         if (d > 0) v = s * p * A.a[d];
@@ -197,15 +203,15 @@ AxisWeights make_axis_weights(int n, double gamma, double p, double g, double dx
         else v = s * (p * 1.0 + (1.0 - p) * 1.0);
         W.T[d + N] = v;
     }
-    for (int j = 1; j <= N; ++j) W.corr0[j] = s * p * A.cp0[j] - W.T[j + N];
-    for (int j = 0; j <= N - 1; ++j) W.corrN[j] = s * (1.0 - p) * A.cmN[j] - W.T[(j - N) + N];
-    const double empty = pow(0.0, gamma);  // c+_{00} = c-_{NN}; T(0) holds 1 there
-    W.corr0[0] = s * p * (empty - 1.0);
-    W.corrN[N] = s * (1.0 - p) * (empty - 1.0);
+    const double empty = pow(0.0, gamma);  // c+_{00} = c-_{NN}
+    for (int j = 1; j <= N; ++j) W.col0[j] = s * p * A.cp0[j];
+    for (int j = 0; j <= N - 1; ++j) W.colN[j] = s * (1.0 - p) * A.cmN[j];
+    W.col0[0] = s * (p * empty + (1.0 - p));
+    W.colN[N] = s * (p + (1.0 - p) * empty);
     if (flux_form == 1) {
         for (int j = 0; j <= N; ++j) {
-            W.corr0[j] -= s * p * (1.0 + gamma) * pow((double)j, gamma);
-            W.corrN[j] -= s * (1.0 - p) * (1.0 + gamma) * pow((double)(N - j), gamma);
+            W.col0[j] -= s * p * (1.0 + gamma) * pow((double)j, gamma);
+            W.colN[j] -= s * (1.0 - p) * (1.0 + gamma) * pow((double)(N - j), gamma);
         }
     }
     return W;
@@ -551,6 +557,7 @@ void build_operator_image(const lbm_grid& grid, const lbm_params& P, unsigned ch
         op.n = n;
         op.lower_only = P.p[mu] == 1.0;
         op.upper_only = P.p[mu] == 0.0;
+        op.ends_excluded = 1;
         const size_t og = carve(sizeof(float) * (2 * n - 1));
         const size_t o0 = carve(sizeof(float) * n);
         const size_t oN = carve(sizeof(float) * n);
@@ -570,9 +577,12 @@ void build_operator_image(const lbm_grid& grid, const lbm_params& P, unsigned ch
             gh[t] = bf16_from_double(v);
             glo[t] = bf16_from_double(v - (double)bf16_to_float(gh[t]));
         }
+        // the whole boundary columns K[j][0] and K[j][N]: the kernels leave
+        // k = 0 and k = N out of the Toeplitz sum, so no product of T with a
+        // wall value is added and then cancelled
         for (int j = 0; j < n; ++j) {
-            c0[j] = (float)W.corr0[j];
-            cN[j] = (float)W.corrN[j];
+            c0[j] = (float)W.col0[j];
+            cN[j] = (float)W.colN[j];
         }
         // pair words of the BF16 split, d decreasing (operand order of the BF16 GEMM)
         uint32_t* pwh = reinterpret_cast<uint32_t*>(host + oph);
@@ -587,8 +597,8 @@ void build_operator_image(const lbm_grid& grid, const lbm_params& P, unsigned ch
             pwl[x] = bits(glo, dd) | (bits(glo, dd - 1) << 16);
         }
         op.gen = reinterpret_cast<const float*>(base + og);
-        op.corr0 = reinterpret_cast<const float*>(base + o0);
-        op.corrN = reinterpret_cast<const float*>(base + oN);
+        op.col0 = reinterpret_cast<const float*>(base + o0);
+        op.colN = reinterpret_cast<const float*>(base + oN);
         op.gen_hi = reinterpret_cast<const uint16_t*>(base + oh);
         op.gen_lo = reinterpret_cast<const uint16_t*>(base + ol);
         op.pw_hi = reinterpret_cast<const uint32_t*>(base + oph);

@@ -11,16 +11,21 @@ namespace lbm {
 constexpr int kMaxQ = 7;
 
 // Device-side description of the fractional operator along one axis
-// (Sec. 2.4): Phi[j] = sum_k T(j - k) C[k] + corr0[j] C[0] + corrN[j] C[N],
-// with T and the boundary corrections pre-multiplied by
-// g dx^gamma / Gamma(2 + gamma) and by p (lower part) / (1 - p) (upper part).
+// (Sec. 2.4), with T and the boundary values pre-multiplied by
+// g dx^gamma / Gamma(2 + gamma) and by p (lower part) / (1 - p) (upper part):
+//   ends_excluded = 1 (the forward operators):
+//     Phi[j] = sum_{0 < k < N} T(j - k) C[k] + col0[j] C[0] + colN[j] C[N],
+//     col0 / colN the whole boundary columns K[j][0], K[j][N];
+//   ends_excluded = 0 (the adjoint's transposed parts):
+//     Phi[j] = sum_{0 <= k <= N} T(j - k) C[k] + col0[j] C[0] + colN[j] C[N].
 struct AxisOp {
     int n;               // nodes on the axis, N = n - 1
     int lower_only;      // p == 1: T(d) = 0 for d < 0
     int upper_only;      // p == 0: T(d) = 0 for d > 0
+    int ends_excluded;   // see above
     const float* gen;    // T(d) at gen[d + n - 1], d in [-(n-1), n-1]
-    const float* corr0;  // n values
-    const float* corrN;  // n values
+    const float* col0;  // n values
+    const float* colN;  // n values
     const uint16_t* gen_hi;  // BF16 bits of T split hi/lo (same indexing)
     const uint16_t* gen_lo;
     // Pair words of the split, W(d) = b(d) | b(d - 1) << 16 with b = hi or lo

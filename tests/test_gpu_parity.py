@@ -38,40 +38,13 @@ def _banner(msg):
     print(f"[gpu-parity] {msg}", flush=True)
 
 
-def _end_terms_at(cfg, Cabs, nodes):
-    """s (|C(x_0)| + |C(x_N)|) of the line through each listed node, per axis."""
-    import math
-
-    d = cfg["dim"]
-    n = cfg["n"][:d]
-    flat = Cabs.reshape(-1)
-    out = np.zeros((d, len(nodes)))
-    strides = [int(np.prod(n[:mu])) for mu in range(d)]
-    for mu in range(d):
-        gam = 2.0 - cfg["alpha"][mu]
-        s_mu = cfg.get("g", [1.0] * d)[mu] * cfg.get("dx", 1.0) ** gam / math.gamma(2.0 + gam)
-        idx = (nodes // strides[mu]) % n[mu]
-        base = nodes - idx * strides[mu]
-        out[mu] = s_mu * (flat[base] + flat[base + (n[mu] - 1) * strides[mu]])
-    return out
-
-
 def _phi_scale(cfg, C, ref):
-    """Magnitude a fractional-term value is formed from, for C >= 0: the value
-    itself (every weight is >= 0) plus s (C(x_0) + C(x_N)), the end terms the
-    kernels add and cancel where c+_00 = c-_NN = 0^gamma (the Toeplitz
-    diagonal holds 1 there), s = g dx^gamma / Gamma(2 + gamma)."""
-    import math
-
-    d = cfg["dim"]
-    scale = np.abs(ref).copy()
-    Cd = np.asarray(C, np.float64)
-    for mu in range(d):
-        ax = d - 1 - mu
-        gam = 2.0 - cfg["alpha"][mu]
-        s_mu = cfg.get("g", [1.0] * d)[mu] * cfg.get("dx", 1.0) ** gam / math.gamma(2.0 + gam)
-        scale[mu] += s_mu * (np.take(Cd, [0], axis=ax) + np.take(Cd, [-1], axis=ax))
-    return scale
+    """Magnitude a fractional-term value is formed from, sum_k |K_jk| |C_k|: for
+    C >= 0 the value itself, since every product-rule weight is >= 0.  (The
+    kernels sum the Toeplitz part over the interior columns and add the two
+    boundary columns K[j][0] C(x_0) and K[j][N] C(x_N) whole, so no product is
+    added and then cancelled.)"""
+    return np.abs(ref)
 
 
 PHI_CASES = [
@@ -103,12 +76,47 @@ def test_fractional_term_matches_oracle(case, precision):
         got = s.apply_phi(torch.from_numpy(C).cuda()).cpu().numpy().astype(np.float64)
         got_host = s.apply_phi(C)
     assert np.array_equal(got, got_host.astype(np.float64))
-    # C >= 0 and every weight >= 0: the scale is sum_k |K||C| (plus the cancelling end terms)
+    # C >= 0 and every weight >= 0: the scale is sum_k |K||C|
     nmax = max(n)
     scale = _phi_scale(cfg, C, ref)
     bound = 4 * nmax * 2.0**-24 * scale + 1e-30
     assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / (scale + 1e-30))
     assert _rel_l2(got, ref) < 2e-6
+
+
+WALL_CASES = [
+    (2, [96, 70], [1.4, 1.7], [1.0, 0.0]),
+    (2, [64, 48], [1.2, 1.9], [0.3, 0.6]),
+    (3, [24, 20, 18], [1.3, 1.6, 1.9], [0.0, 1.0, 0.5]),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_simt", "bf16x3"])
+@pytest.mark.parametrize("case", WALL_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
+def test_wall_dominated_phi_within_its_own_magnitude(case, precision):
+    """C = 1 on every wall and 1e-3 inside.  Each Phi value must be within
+    eps-scaled sum_k |K_jk| |C_k| of the oracle, wall rows included: where the
+    one-sided integral is empty (row 0 of I+, row N of I-) that magnitude is the
+    other integral's alone, so a kernel that added s C(x_0) on the Toeplitz
+    diagonal and cancelled it in the boundary column would fail here."""
+    dim, n, alpha, p = case
+    _banner(f"wall-dominated phi {precision} dim={dim} n={n}")
+    cfg = synth.small(dim, n, alpha=alpha, p=p, seed=31)
+    cfg["g"] = [0.9, 1.4, 1.2][:dim]
+    cfg["dx"] = 0.25
+    C = np.full(synth.shape(cfg), 1e-3, np.float32)
+    for ax in range(dim):
+        idx = [slice(None)] * dim
+        idx[ax] = 0
+        C[tuple(idx)] = 1.0
+        idx[ax] = -1
+        C[tuple(idx)] = 1.0
+    ref = oracle.phi(cfg, C.astype(np.float64))
+    with _solver(cfg, precision) as s:
+        got = s.apply_phi(torch.from_numpy(C).cuda()).cpu().numpy().astype(np.float64)
+    scale = _phi_scale(cfg, C, ref)  # C >= 0: sum_k |K||C| is the value itself
+    rel = 4 * max(n) * 2.0**-24 if precision != "bf16x3" else 2.0**-14
+    assert np.all(np.abs(got - ref) <= rel * scale + 1e-30), np.max(np.abs(got - ref) / (scale + 1e-30))
 
 
 @pytest.mark.parametrize("case", PHI_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
@@ -360,8 +368,7 @@ def test_full_size_phi_per_axis(name, precision):
     20 steps: the GEMM launch of a step against the oracle's direct sums at
     sampled nodes.  Errors are measured against sum_k |K||C| of the same node,
     which is the oracle's Phi of |C| because every product-rule weight is
-    >= 0 (C itself changes sign after a few steps, so Phi can cancel), plus the
-    end terms of _phi_scale."""
+    >= 0 (C itself changes sign after a few steps, so Phi can cancel)."""
     cfg = synth.config(name)
     _banner(f"full-size phi per axis {name} {precision}")
     with _solver(cfg, precision) as s:
@@ -372,7 +379,6 @@ def test_full_size_phi_per_axis(name, precision):
     nodes = _sample_nodes(cfg, 400, 11)
     ref = oracle.phi_at(cfg, C.astype(np.float64), nodes)
     mag = oracle.phi_at(cfg, np.abs(C).astype(np.float64), nodes)  # sum_k |K||C|
-    mag = mag + _end_terms_at(cfg, np.abs(C).astype(np.float64), nodes)
     bound = 4 * max(cfg["n"]) * 2.0**-24 if precision == "fp32" else 2.0**-14
     for mu in range(cfg["dim"]):
         g, r = got[mu, nodes].astype(np.float64), ref[mu]
