@@ -568,14 +568,21 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
     const bool lane_k0 = ends && kw == 0 && lh == 0;
     const bool lane_kN = ends && lh == (N % 8) / 4;
     const int g_kN = (ends && N >= kw && N < kw + 8 * my_groups) ? (N - kw) / 8 : -1;
-    auto kill_kN = [&](int g, f32x4& v) {
+    // C of group g as the MFMAs take it: zero past the end of the range (those
+    // groups re-read the last one), and k = N left out.  One select per
+    // element either way: with n % 8 == 0 the k = N condition only widens the
+    // last element's mask.
+    auto zero_dead_and_kN = [&](int g, f32x4& v) {
+        const bool dead = g >= my_groups;
         const bool kn = lane_kN && g == g_kN;
         if constexpr (KFULL) {
-            v[3] = kn ? 0.f : v[3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[e] = dead ? 0.f : v[e];
+            v[3] = (dead || kn) ? 0.f : v[3];
         } else {
             const int e_kN = N % 4;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (kn && e == e_kN) ? 0.f : v[e];
+            for (int e = 0; e < 4; ++e) v[e] = (dead || (kn && e == e_kN)) ? 0.f : v[e];
         }
     };
 
@@ -673,8 +680,7 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
                 const int g = g0 + u;
                 // C of this group (zero past the end of the range), then reuse its slot for group g + P
                 f32x4 cur = craw[u % P];
-                if (g >= my_groups) cur = f32x4{0.f, 0.f, 0.f, 0.f};
-                kill_kN(g, cur);
+                zero_dead_and_kN(g, cur);
                 load_c(g + P, craw[u % P]);
                 load_t(g + 1, tf[(u + 1) & 1]);
 #pragma unroll
