@@ -659,11 +659,15 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         });
         return hipGetLastError();
     }
-    // NY = 8 rows per workgroup (one wave per row, 6 output rows): two
-    // workgroups share a CU, and the y-halo rows of one come from L2 lines its
-    // neighbour on the same XCD has fetched.  At 256^3, 313 us against 322
-    // with 16-row workgroups; the space-dependent variant (9 more values per
-    // ring plane, up to 256 VGPRs) also needs the smaller workgroup.
+    // Rows per workgroup (one wave per row, the first and last are halo):
+    // NY = 10 (8 output rows, so 8 | ny tiles the usual sizes exactly) for the
+    // constant tensor: two workgroups fill a CU's 20 wave slots at 86 VGPRs,
+    // and the y-halo rows come from L2 lines the neighbouring workgroup on the
+    // same XCD fetched.  Measured at 256^3 (kernel trace; L2 fetches against
+    // the algorithmic reads): NY = 8 with 16-plane marches 308.2 us, 1.43x;
+    // NY = 10 with 16 planes 304.6 us, 1.16x; with 32 planes 290.7 us, 1.11x;
+    // NY = 12 or 16 were slower (one workgroup per CU).  The space-dependent
+    // variant (9 more values per ring plane, up to 256 VGPRs) keeps NY = 8.
     auto launch3d = [&](auto ny_c, auto hs, auto vr, auto ntc) {
         constexpr int NY = decltype(ny_c)::value;
         const int nx = cc.n[0], ny = cc.n[1], nz = cc.n[2];
@@ -671,13 +675,16 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
         const int sy = (ny + (NY - 2) - 1) / (NY - 2);
         // Long z marches amortise the two halo planes; a queue of several
         // workgroups per CU lets a new one start its ring while the others
-        // march.  Measured on MI355X (8 / 16 / 32 / 64 planes): 128^3 33 / 38 /
-        // 39 / 69 us, 256^3 319 / 309 / 312 / 318, 384^3 1019 / 975 / 946 / 939:
-        // the longest march that still gives 2048 workgroups.
+        // march.  Measured on MI355X with NY = 8 (8 / 16 / 32 / 64 planes):
+        // 128^3 33 / 38 / 39 / 69 us, 256^3 319 / 309 / 312 / 318, 384^3 1019 /
+        // 975 / 946 / 939: the longest march that still gives 2048 workgroups;
+        // with NY = 10 (256^3: 16 planes 304.6 us, 32 planes 290.7 us) the
+        // longest that gives 1024.
         int planes = collide_rows_override();
         if (planes <= 0) {
+            const int64_t want = NY == 8 ? 2048 : 1024;
             planes = 64;
-            while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < 2048) planes /= 2;
+            while (planes > 8 && (int64_t)sx * sy * ((nz + planes - 1) / planes) < want) planes /= 2;
         }
         const int chunks = (nz + planes - 1) / planes;
         const int64_t blocks = (int64_t)sx * sy * chunks;
@@ -690,7 +697,10 @@ hipError_t launch_collide_stream(const CollideConsts& cc, const float* f_in, flo
     };
     hipError_t e = hipSuccess;
     with_flags(S != nullptr, var, nt, [&](auto hs, auto vr, auto ntc) {
-        e = launch3d(std::integral_constant<int, 8>{}, hs, vr, ntc);
+        if constexpr (decltype(vr)::value)
+            e = launch3d(std::integral_constant<int, 8>{}, hs, vr, ntc);
+        else
+            e = launch3d(std::integral_constant<int, 10>{}, hs, vr, ntc);
     });
     if (e != hipSuccess) return e;
     return hipGetLastError();
