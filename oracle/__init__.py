@@ -84,6 +84,7 @@ def lib():
             "fo_step_var": (ctypes.c_int, [P, dp, dp, dp, dp, ctypes.c_int64]),
             "fo_step_sampled": (ctypes.c_int, [P, dp, dp, ip, ctypes.c_int64, dp]),
             "fo_threads": (ctypes.c_int, []),
+            "fo_flush_subnormals": (ctypes.c_int, [ctypes.c_int]),
         }
         sig["fo_adjoint"] = (ctypes.c_int, [P, dp, dp, ctypes.c_int64, dp, dp, dp, dp, dp, dp])
         for name, (res, args) in sig.items():
@@ -281,6 +282,13 @@ def step_sampled(cfg: dict, f: np.ndarray, nodes: np.ndarray, S: np.ndarray | No
 def threads() -> int:
     """Threads the oracle's parallel loops use (OpenMP)."""
     return int(lib().fo_threads())
+
+
+def flush_subnormals(on: bool = True) -> None:
+    """Read and write subnormal FP64 values as zero in the oracle's threads (x86
+    DAZ/FTZ; see fo_flush_subnormals).  For long golden runs only."""
+    if int(lib().fo_flush_subnormals(1 if on else 0)) != 0:
+        raise RuntimeError("subnormal flushing is not available on this CPU")
 
 
 def run(cfg: dict, C0: np.ndarray, nsteps: int, S: np.ndarray | None = None) -> np.ndarray:

@@ -10,10 +10,14 @@ shorter run can be checked against the same reference.
 Long runs can be split: ``--checkpoint DIR`` saves the FP64 populations every
 ``--every`` steps and resumes from the newest saved state (the step loop is
 the oracle's, so a resumed run equals an uninterrupted one bit for bit).
+``--flush-subnormals`` reads and writes FP64 values below 2.2e-308 as zero:
+the 4096^2 run's fractional tails fill many nodes with such values, which the
+x86 FPU handles slowly enough to stall it; the change per value is below
+1e-300.
 
     python tests/golden/make_reference.py c2_1024sq
-    python tests/golden/make_reference.py c4_4096sq --stride 8 --marks 1,10,100 \\
-        --checkpoint /some/scratch/dir --every 50
+    python tests/golden/make_reference.py c4_4096sq --stride 8 --marks 10,100 \\
+        --checkpoint /some/scratch/dir --every 50 --flush-subnormals
 """
 import argparse
 import glob
@@ -50,7 +54,7 @@ def _latest_checkpoint(ckdir: str, name: str):
 
 
 def make(name: str, steps: int | None = None, stride: int | None = None, marks=(), checkpoint: str | None = None,
-         every: int = 50) -> str:
+         every: int = 50, flush_subnormals: bool = False) -> str:
     cfg = synth.config(name)
     steps = cfg["steps"] if steps is None else steps
     stride = stride_of(cfg["dim"]) if stride is None else stride
@@ -76,6 +80,10 @@ def make(name: str, steps: int | None = None, stride: int | None = None, marks=(
             print(f"{name}: resuming at step {done} from {path}", flush=True)
     if f is None:
         f = oracle.init(cfg, C0)
+    flushed_from = -1  # first step computed with subnormals flushed (-1: none)
+    if flush_subnormals:
+        oracle.flush_subnormals(True)
+        flushed_from = done
     while done < steps:
         # advance to the next mark, checkpoint or the end, whichever comes first
         nxt = min([steps] + [m for m in marks if m > done] + ([done + every - done % every] if checkpoint else []))
@@ -99,7 +107,8 @@ def make(name: str, steps: int | None = None, stride: int | None = None, marks=(
     extra = {f"C_at_{m}": snap[m] for m in marks if m in snap}
     np.savez(path, C=C[sl], name=name, steps=steps, stride=stride, full_l2=np.linalg.norm(C.ravel()),
              seconds=dt, threads=oracle.threads(), marks=np.array(sorted(extra and [int(k[5:]) for k in extra]),
-                                                                  dtype=np.int64), **extra)
+                                                                  dtype=np.int64),
+             subnormals_flushed_from_step=flushed_from, **extra)
     print(f"{name}: {steps} steps in {dt:.1f} s on {oracle.threads()} threads -> {path}")
     return path
 
@@ -112,5 +121,8 @@ if __name__ == "__main__":
     ap.add_argument("--marks", default="", help="comma-separated step counts whose C is also stored")
     ap.add_argument("--checkpoint", default=None, help="directory for resumable FP64 population checkpoints")
     ap.add_argument("--every", type=int, default=50)
+    ap.add_argument("--flush-subnormals", action="store_true",
+                    help="treat FP64 values below 2.2e-308 as zero (speed of very long runs)")
     a = ap.parse_args()
-    make(a.name, a.steps, a.stride, [int(m) for m in a.marks.split(",") if m], a.checkpoint, a.every)
+    make(a.name, a.steps, a.stride, [int(m) for m in a.marks.split(",") if m], a.checkpoint, a.every,
+         a.flush_subnormals)

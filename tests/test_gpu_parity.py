@@ -455,28 +455,41 @@ def test_zero_steps_and_repeat_calls_are_consistent():
 
 
 @pytest.mark.parametrize("name,precision,bound", [("c2_1024sq", "fp32", 1e-5), ("c2_1024sq", "bf16x3", 1e-4),
-                                                  ("c3_256cube", "fp32", 1e-5), ("c3_256cube", "bf16x3", 1e-4)])
+                                                  ("c3_256cube", "fp32", 1e-5), ("c3_256cube", "bf16x3", 1e-4),
+                                                  ("c4_4096sq", "fp32", 1e-5), ("c4_4096sq", "bf16x3", 1e-4)])
 def test_full_workload_against_stored_oracle(name, precision, bound):
     """The workloads at full size and full step count (1024^2 x 2000 steps;
-    256^3 x 500 steps with its point source) against the stored FP64 oracle
-    result (every 4th node in 2D, every 8th in 3D; tests/golden/make_reference.py)."""
+    256^3 x 500 steps with its point source; 4096^2 x 1000 steps) against the
+    stored FP64 oracle result on the sub-grid of every stride-th node
+    (tests/golden/make_reference.py; 4, 8 and 8 here), and at the intermediate
+    step counts the file also holds."""
+    import glob
     import os
 
     from conftest import GOLDEN
 
     cfg = synth.config(name)
-    stride = 4 if cfg["dim"] == 2 else 8
-    path = os.path.join(GOLDEN, f"ref_{name}_{cfg['steps']}steps_every{stride}.npz")
-    ref = np.load(path)
-    _banner(f"full workload {name} {precision}")
+    hits = sorted(glob.glob(os.path.join(GOLDEN, f"ref_{name}_{cfg['steps']}steps_every*.npz")))
+    assert hits, f"no stored oracle result for {name}"
+    ref = np.load(hits[0])
+    stride = int(ref["stride"])
+    marks = [int(m) for m in ref["marks"]] if "marks" in ref.files else []
+    _banner(f"full workload {name} {precision} (marks {marks})")
     S = synth.source(cfg)
+    sl = (slice(None, None, stride),) * cfg["dim"]
+    errs = {}
     with _solver(cfg, precision) as s:
         s.set_C(synth.initial_C(cfg).astype(np.float32))
         if S is not None:
             s.set_source(S.astype(np.float32))
-        s.step(cfg["steps"])
-        C = s.get_C(device=False)
-    sl = (slice(None, None, stride),) * cfg["dim"]
-    err = _rel_l2(C[sl], ref["C"])
-    print(f"[gpu-parity] {name} {precision} rel L2 vs stored oracle = {err:.3e}", flush=True)
-    assert err <= bound
+        done = 0
+        for m in marks + [cfg["steps"]]:
+            s.step(m - done)
+            done = m
+            C = s.get_C(device=False)
+            want = ref["C"] if m == cfg["steps"] else ref[f"C_at_{m}"]
+            errs[m] = _rel_l2(C[sl], want)
+    print(f"[gpu-parity] {name} {precision} rel L2 vs stored oracle by step: "
+          + ", ".join(f"{m}: {e:.3e}" for m, e in errs.items()), flush=True)
+    for m, e in errs.items():
+        assert e <= bound, (m, e)

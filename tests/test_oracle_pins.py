@@ -592,3 +592,30 @@ def test_invalid_parameters_rejected(oracle_lib):
     for cfg in bad:
         with pytest.raises(ValueError):
             oracle_lib.run(cfg, np.zeros((6, 6)) if cfg["n"][0] == 6 else np.zeros((6, 2)), 1)
+
+
+def test_subnormal_flush_changes_nothing_in_the_normal_range(oracle_lib):
+    """The golden generator's opt-in subnormal flush (x86 DAZ/FTZ in the oracle's
+    threads) may only alter values below the FP64 normal range: a run whose
+    tails stay normal is bit-identical with and without it, and a run seeded
+    with subnormal concentrations differs from the unflushed run by less than
+    1e-300 anywhere."""
+    cfg = synth.small(2, [40, 33], alpha=[1.3, 1.7], p=[1.0, 0.0], seed=21)
+    C0 = synth.initial_C(cfg)
+    a = oracle_lib.run(cfg, C0, 15)
+    tiny = np.finfo(np.float64).tiny
+    C1 = C0.copy()
+    C1[5:9, 5:30] = 0.25 * tiny  # subnormal
+    b = oracle_lib.run(cfg, C1, 15)
+    try:
+        oracle_lib.flush_subnormals(True)
+        af = oracle_lib.run(cfg, C0, 15)
+        bf = oracle_lib.run(cfg, C1, 15)
+    finally:
+        oracle_lib.flush_subnormals(False)
+    if np.any((np.abs(a) > 0) & (np.abs(a) < tiny)):
+        assert np.max(np.abs(af - a)) < 1e-300
+    else:
+        assert np.array_equal(af, a)
+    assert np.max(np.abs(bf - b)) < 1e-300
+    assert np.array_equal(oracle_lib.run(cfg, C0, 15), a)  # flush is off again
