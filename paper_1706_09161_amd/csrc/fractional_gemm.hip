@@ -961,6 +961,8 @@ hipError_t run_f32_auto(FracLaunch& L, hipStream_t s)
     case 12: return run_f32_ring<8, 4, 1, 2>(L, s);
     case 13: return run_f32_ring<2, 1, 4, 2>(L, s);
     case 14: return run_f32_ring<2, 2, 2, 2>(L, s);
+    case 15: return run_f32_ring<4, 1, 4, 1>(L, s);
+    case 16: return run_f32_ring<4, 2, 2, 1>(L, s);
     default: break;
     }
     // Register-direct kernel: a large output tile that still fills the chip.
@@ -971,7 +973,12 @@ hipError_t run_f32_auto(FracLaunch& L, hipStream_t s)
     // Measured on MI355X (kernel trace, us): 64^3 21.8 -> 10.6, 96^3 43.7 ->
     // 20.6, 128^3 54.1 -> 26.9, 128^2 11.5 -> 5.9, 256^2 15.4 -> 7.0 against
     // 256-output tiles on grids below 512 workgroups; 384^3 1250 -> 1160
-    // with the 2-way split in place of unsplit 128-line tiles.
+    // with the 2-way split in place of unsplit 128-line tiles.  The 128-output
+    // tiles prefetch C one group ahead (P = 1: fewer registers, a 2-group
+    // unroll): kernel trace, us, P = 2 -> 1: 4096^2 1130.8 -> 1110.2, 2048^2
+    // 280.4 -> 273.9, 1024^2 39.8 -> 39.2 (4-way split); 96^3 17.8 -> 15.2,
+    // 128^3 25.8 -> 25.5 (2-way split); the 256- and 64-output tiles keep
+    // P = 2 (256^3 249.0 against 250.4 with P = 1; 512^2 9.5 against 10.6).
     int nmax = 0, nmin = 1 << 30;
     for (int a = 0; a < L.naxes; ++a) {
         nmax = L.op[a].n > nmax ? L.op[a].n : nmax;
@@ -986,9 +993,9 @@ hipError_t run_f32_auto(FracLaunch& L, hipStream_t s)
         if (grid >= 512) return run_f32_ring<8, 4, 1, 2>(L, s);
     }
     f32_ring_grid<4, 2, 2>(T, grid, lds);
-    if (grid >= 512 && (kgroups + 1) / 2 <= 128) return run_f32_ring<4, 2, 2, 2>(L, s);
+    if (grid >= 512 && (kgroups + 1) / 2 <= 128) return run_f32_ring<4, 2, 2, 1>(L, s);
     f32_ring_grid<4, 1, 4>(T, grid, lds);
-    if (grid >= 256) return run_f32_ring<4, 1, 4, 2>(L, s);
+    if (grid >= 256) return run_f32_ring<4, 1, 4, 1>(L, s);
     // small grids: output tiles of 64 so that every CU gets a workgroup
     return run_f32_ring<2, 1, 4, 2>(L, s);
 }
@@ -1008,11 +1015,11 @@ int64_t big_tiles(const FracLaunch& L)
 
 int tile_choice(const char* var)
 {
-    // 0 = automatic; 1..14 = the explicit configurations listed at the call sites
+    // 0 = automatic; 1..16 = the explicit configurations listed at the call sites
     const char* v = getenv(var);
     if (!v || !*v) return 0;
     const int c = atoi(v);
-    return (c >= 1 && c <= 14) ? c : 0;
+    return (c >= 1 && c <= 16) ? c : 0;
 }
 
 }  // namespace lbm

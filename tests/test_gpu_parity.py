@@ -145,7 +145,7 @@ TILE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("choice", [f"fp32:{c}" for c in range(1, 15)] + [f"bf16x3:{c}" for c in range(1, 15)])
+@pytest.mark.parametrize("choice", [f"fp32:{c}" for c in range(1, 17)] + [f"bf16x3:{c}" for c in range(1, 15)])
 @pytest.mark.parametrize("case", TILE_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
 def test_every_tile_configuration(case, choice, monkeypatch):
     """Each explicitly selectable GEMM configuration (LBM_FP32_TILE / LBM_BF16_TILE)
