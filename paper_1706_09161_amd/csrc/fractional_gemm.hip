@@ -464,10 +464,12 @@ hipError_t run_f32(FracLaunch& L, hipStream_t s)
 // lane consumes 4 consecutive k: at step s of group g the lane half lh works
 // on k = kw + 8 KSPLIT g + 4 lh + s (both operands use the same map, so the
 // sum is unchanged).  Dealing the groups round robin puts every stretch of
-// large products (a pulse in C) into all KSPLIT accumulators rather than one:
-// each FP32 running sum is then about 1/KSPLIT of the total, and so is its
-// rounding error (at 4096^2 after 100 steps the C error against the FP64
-// oracle is 6.4e-6 instead of 1.5e-5 with contiguous k shares).  Hence
+// large products (a pulse in C) into all KSPLIT accumulators rather than one,
+// and with 128-output tiles each wavefront alternates its groups between two
+// accumulator sets: each FP32 running sum is then about 1/(2 KSPLIT) of the
+// total, and so is its rounding error (at 4096^2 after 100 steps the C error
+// against the FP64 oracle is 4.5e-6, 6.4e-6 with one set per wavefront,
+// 1.5e-5 with contiguous k shares).  Hence
 //  * C comes straight from global memory into registers, P groups ahead, one
 //    16-byte load per lane and group along the contiguous axis (4 loads,
 //    coalesced across consecutive lines, along a strided axis; the KSPLIT
@@ -662,11 +664,20 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
     lds_barrier();  // the C prefetch stays in flight
     craw[0][0] = lane_k0 ? 0.f : craw[0][0];  // k = 0 is only ever in group 0
 
-    f32x16 acc[NBJ];
+    // Two accumulator sets where registers allow (NBJ <= 4): groups alternate
+    // between them, so each FP32 running sum takes half of the wavefront's
+    // products (see the rounding note above the kernel).
+    constexpr bool TWO = NBJ <= 4;
+    constexpr int NA = TWO ? NBJ : 1;
+    f32x16 acc[NBJ], acc2[NA];
 #pragma unroll
     for (int c = 0; c < NBJ; ++c)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NA; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc2[c][r] = 0.f;
 
     if (my_groups > 0) {
         // Toeplitz values of block c, group g: window words m0 .. m0 + 3
@@ -695,10 +706,11 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
                 for (int st = 0; st < 4; ++st)
 #pragma unroll
                     for (int c = 0; c < NBJ; ++c) {
+                        f32x16& a = (TWO && (u & 1)) ? acc2[TWO ? c : 0] : acc[c];
                         if constexpr (CONTIG)
-                            acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[st], tf[u & 1][c][st], acc[c], 0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[st], tf[u & 1][c][st], a, 0, 0, 0);
                         else
-                            acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(tf[u & 1][c][st], cur[st], acc[c], 0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(tf[u & 1][c][st], cur[st], a, 0, 0, 0);
                     }
 #pragma unroll
                 for (int i = 0; i < 4 * NBJ; ++i) {
@@ -712,6 +724,12 @@ __device__ __forceinline__ void f32_ring_tile(const AxisOp& op, const AxisLayout
         }
     }
 
+    if constexpr (TWO) {
+#pragma unroll
+        for (int c = 0; c < NBJ; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[c][r] += acc2[TWO ? c : 0][r];
+    }
     // The output of a wavefront is NBJ blocks x 4 groups of 4 rows ("units",
     // u = 4 c + r4).  With k split across waves, the partial tiles are summed
     // through LDS and the units are dealt out to the KSPLIT wavefronts.
