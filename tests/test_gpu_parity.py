@@ -149,7 +149,8 @@ TILE_CASES = [
 @pytest.mark.parametrize("case", TILE_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
 def test_every_tile_configuration(case, choice, monkeypatch):
     """Each explicitly selectable GEMM configuration (LBM_FP32_TILE / LBM_BF16_TILE)
-    against the oracle, with the bounds of the default path."""
+    against the oracle, with the bounds of the default path.  The output buffer
+    starts as NaN, so a tile that leaves an output unwritten fails."""
     precision, c = choice.split(":")
     dim, n, alpha, p = case
     _banner(f"phi {precision} tile {c} dim={dim} n={n}")
@@ -159,7 +160,10 @@ def test_every_tile_configuration(case, choice, monkeypatch):
     C = rng.uniform(0.0, 1.0, synth.shape(cfg)).astype(np.float32)
     ref = oracle.phi(cfg, C.astype(np.float64))
     with _solver(cfg, precision) as s:
-        got = s.apply_phi(torch.from_numpy(C).cuda()).cpu().numpy().astype(np.float64)
+        out = torch.full((dim,) + tuple(C.shape), float("nan"), device="cuda")
+        s.apply_phi(torch.from_numpy(C).cuda(), out=out)
+        got = out.cpu().numpy().astype(np.float64)
+    assert np.isfinite(got).all(), int(np.count_nonzero(~np.isfinite(got)))
     rel = 4 * max(n) * 2.0**-24 if precision == "fp32" else 2.0**-14
     scale = _phi_scale(cfg, C, ref)
     assert np.all(np.abs(got - ref) <= rel * scale + 1e-30), np.max(np.abs(got - ref) / scale)
