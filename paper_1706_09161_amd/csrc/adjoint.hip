@@ -53,8 +53,44 @@ struct AdjConsts {
     float wdt[kMaxQ];        // w_i dt
 };
 
+// One 64-bit value moved between lanes by a DPP control (both halves alike);
+// lanes of the rows outside ROWS get 0.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xF, false);
+    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xF, false);
+    return __hiloint2double(h2, l2);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// FP64 sum over the 64 lanes of a wavefront, taken from lane 63: rotations by
+// 8, 4, 2 and 1 lanes inside each row of 16 (DPP row_ror; every source lane
+// exists) leave each row's sum in its lanes; row_bcast:15 then adds row 0's sum
+// into row 1 and row 2's into row 3, and row_bcast:31 adds that of rows 0-1
+// (lane 31) into rows 2-3.  Fixed order, no LDS traffic.
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    x += dpp_f64<0x128>(x);       // row_ror:8
+    x += dpp_f64<0x124>(x);       // row_ror:4
+    x += dpp_f64<0x122>(x);       // row_ror:2
+    x += dpp_f64<0x121>(x);       // row_ror:1
+    x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return readlane_f64(x, 63);
+}
+
 // Sum `v` over the workgroup in FP64 (fixed order) into out[0..NV): stored, or
 // (ACC) added to what the slot holds (the workgroup's running sum over steps).
+// Every thread of the workgroup must call it (the lane exchanges read all 64
+// lanes).
 template <int NV, bool ACC = false>
 __device__ inline void block_sum_store(double (&v)[NV], double* __restrict__ out)
 {
@@ -62,9 +98,7 @@ __device__ inline void block_sum_store(double (&v)[NV], double* __restrict__ out
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        double x = v[k];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+        const double x = wave_sum_f64(v[k]);
         if (lane == 0) sh[wave][k] = x;
     }
     __syncthreads();
